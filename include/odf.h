@@ -1,0 +1,229 @@
+/*
+ * odf.h - C ABI of the MI355X opacity-distribution-function (ODF) engine.
+ *
+ * The engine computes, for every (composition, microturbulence, temperature,
+ * pressure) point, the line opacity of a line list on a logarithmic
+ * wavelength grid of resolving power R and collapses every wavelength bin of
+ * that grid into a step function of sub-bin mean opacities: the ODF table of
+ * MPS-ATLAS module I (Witzke et al. 2021, "MPS-ATLAS: a fast all-in-one code
+ * for synthesising stellar spectra"; Sec. 2.3 "The ODF approach" and App. E
+ * "ODF and opacity calculations").
+ *
+ * Inputs follow the paper's statement of the module-I problem (Sec. 3,
+ * module-I inputs of the code-structure figure): elemental composition, a
+ * line list, the turbulent velocity, the temperature-pressure grid, the
+ * wavelength range and the bin / sub-bin configuration.  Output is the ODF
+ * table.  Every computational step runs on the GPU.
+ *
+ * Conventions
+ *   - All functions return odf_status (0 = ODF_OK, < 0 = error).  On error a
+ *     message is available from odf_last_error() (thread-local).  No C++
+ *     exception crosses this interface.
+ *   - "host" pointers are read during the call only and may be freed after it
+ *     returns.  "device" pointers are HIP device allocations owned by the
+ *     caller (for example PyTorch tensors) and must stay valid for as long as
+ *     stated for each field.
+ *   - Units are CGS unless stated; wavelengths in nm (vacuum).
+ */
+#ifndef ODF_H
+#define ODF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ODF_OK = 0,
+  ODF_E_INVALID = -1,        /* malformed argument; message says which */
+  ODF_E_NOMEM = -2,          /* workspace too small for the request */
+  ODF_E_DEVICE = -3,         /* a HIP call failed */
+  ODF_E_UNKNOWN_TICKET = -4, /* odf_poll/odf_wait on a ticket never issued */
+  ODF_E_CANCELLED = -5,      /* plan destroyed while the request waited */
+  ODF_E_INTERNAL = -6        /* invariant broken inside the library */
+} odf_status;
+
+typedef enum {
+  ODF_PREC_FP64 = 0,  /* FP64 everywhere: accurate W(z), FP64 sums, FP64 ODF */
+  ODF_PREC_MIXED = 1  /* FP64 line strengths; FP32 Voigt with compensated sums;
+                         FP32 sort keys; FP64 step sums; FP32 ODF output */
+} odf_precision;
+
+typedef enum {
+  ODF_MEAN_GEOMETRIC = 0,  /* sub-bin geometric mean (the paper's default, Sec. 2.3) */
+  ODF_MEAN_ARITHMETIC = 1  /* 'odf mean arithmetic' (App. G, module-I keywords) */
+} odf_mean;
+
+typedef enum { ODF_PENDING = 0, ODF_RUNNING = 1, ODF_DONE = 2, ODF_FAILED = 3 } odf_state;
+
+/* Line list, structure of arrays, any order (host).  The plan sorts a copy
+ * by wavelength and keeps it resident on the device.
+ *   lambda_nm    vacuum wavelength of the transition
+ *   log_gf       log10 of g_i f_ij (Sec. 2.1, eq. l_nu_line)
+ *   e_low_ev     energy of the lower level E_i
+ *   species      0..n_species-1;  stage 0..n_stages-1 (0 = neutral)
+ *   log_g_rad    log10 radiative damping [s^-1]
+ *   log_g_stark  log10 quadratic-Stark damping per electron at 10^4 K [s^-1 cm^3]
+ *   log_g_vdw    log10 van der Waals damping per heavy particle at 10^4 K [s^-1 cm^3]
+ * The total damping constant (Sec. 2.1) is
+ *   gamma = g_rad + g_stark n_e (T/1e4)^(1/6) + g_vdw N_heavy (T/1e4)^0.3. */
+typedef struct {
+  int64_t n_lines;
+  const double *lambda_nm, *log_gf, *e_low_ev;
+  const int32_t *species, *stage;
+  const double *log_g_rad, *log_g_stark, *log_g_vdw;
+} odf_lines;
+
+/* Species table (host).
+ *   mass_amu  [n_species]                  atomic mass (Doppler width, App. E)
+ *   chi_ev    [n_species][n_stages-1]      ionisation energy of stage k -> k+1
+ *   part_fn   [n_species][n_stages]        partition function U_k (T-independent) */
+typedef struct {
+  int32_t n_species, n_stages;
+  const double *mass_amu, *chi_ev, *part_fn;
+} odf_species;
+
+/* Wavelength grid and bin / sub-bin layout (host).
+ * Fine grid: lambda_j = lambda_first_nm * (1 + 1/R)^j, j = 0..N-1, N the
+ * number of points not beyond lambda_last_nm (App. E grid formula, 0-based).
+ *   bin_edges [n_bins+1] fine indices, strictly increasing, 0 <= e < = N.
+ *             Bin b covers [bin_edges[b], bin_edges[b+1]); any width
+ *             1..20000 points is accepted (user-defined binning, App. E).
+ *   step_frac [n_steps] sub-bin widths as fractions of the bin, > 0, summing
+ *             to 1 within 1e-9, listed from the lowest opacity upward. */
+typedef struct {
+  double lambda_first_nm, lambda_last_nm, resolving_power;
+  int32_t n_bins;
+  const int64_t *bin_edges;
+  int32_t n_steps;
+  const double *step_frac;
+} odf_layout;
+
+/* Plan options.
+ *   cutoff            line pre-selection factor (Sec. 4.3): a line is kept if
+ *                     its core opacity S*H(0,a) >= cutoff*kappa_c(lambda_0);
+ *                     its window ends where its envelope drops below that
+ *                     level; the fine-grid opacity is floored at it.
+ *   window_cap_doppler cap of the half-window in Doppler widths.
+ *   pe_over_p         electron pressure as a fraction of the gas pressure.
+ *   kappa_c_*         continuum kappa_c(lambda) = ref * (lambda/lambda_ref)^power [cm^2/g].
+ *   workspace         caller-owned device memory used for all intermediate
+ *                     data; must outlive the plan.  Its size bounds the number
+ *                     of points processed together and the number of requests
+ *                     the request loop admits at once.
+ *   stream            hipStream_t used by odf_compute (NULL = default stream).
+ *   max_batch_points  upper bound on points per device batch (0 = automatic).
+ *   loop_streams      streams used by the request loop (0 = 2). */
+typedef struct {
+  odf_precision precision;
+  odf_mean mean;
+  double cutoff;
+  double window_cap_doppler;
+  double pe_over_p;
+  double kappa_c_ref, lambda_c_ref_nm, kappa_c_power;
+  void *workspace;
+  int64_t workspace_bytes;
+  void *stream;
+  int32_t max_batch_points;
+  int32_t loop_streams;
+} odf_options;
+
+/* One ODF request.
+ *   abundance  host [n_species] number ratio N_s/N_H, > 0
+ *   T_K, log10_P_cgs, vturb_kms  host [n_points] point list (a T-P grid and a
+ *              list of microturbulences, App. G 'velocities values' and the
+ *              odf.tpgrid file, expanded by the caller)
+ *   out        device buffer [n_points][n_bins][n_steps] of double (FP64) or
+ *              float (MIXED), caller-owned, written in full; valid once
+ *              odf_compute returns or odf_poll reports ODF_DONE. */
+typedef struct {
+  const double *abundance;
+  int32_t n_points;
+  const double *T_K, *log10_P_cgs, *vturb_kms;
+  void *out;
+} odf_request;
+
+/* Per-request statistics.  Times are seconds on a monotonic clock.
+ *   line_evals    lines considered, summed over points (selection included)
+ *   survivors     kept lines with a non-empty window, summed over points
+ *   voigt_samples profile samples added to the grid, summed over points */
+typedef struct {
+  odf_state state;
+  double t_submit, t_admit, t_done;
+  int64_t points, line_evals, survivors, voigt_samples;
+  char msg[128];
+} odf_stats;
+
+typedef struct odf_plan_s odf_plan_t;
+
+/* Build a plan: validates and copies every host array, sorts the lines by
+ * wavelength, uploads them and the per-line constants (App. E first stage,
+ * items i-iii, per line) and sizes the workspace.  *out receives the plan.
+ * Errors: ODF_E_INVALID (bad argument), ODF_E_NOMEM (workspace smaller than
+ * one point needs), ODF_E_DEVICE. */
+odf_status odf_plan(const odf_lines *lines, const odf_species *species,
+                    const odf_layout *layout, const odf_options *opts,
+                    odf_plan_t **out);
+
+/* Compute one request on options.stream and wait for it (App. E, stages one
+ * to three for every point).  Must not run concurrently with another
+ * odf_compute on the same plan.  stats may be NULL. */
+odf_status odf_compute(odf_plan_t *plan, const odf_request *req, odf_stats *stats);
+
+/* Queue a request for the plan's request loop and return at once.  The host
+ * arrays are copied; req->out must stay valid until the ticket is final.
+ * ODF_E_NOMEM if the request can never fit the workspace. */
+odf_status odf_submit(odf_plan_t *plan, const odf_request *req, int64_t *ticket);
+
+/* Non-blocking status of a ticket; DONE and FAILED are final. */
+odf_status odf_poll(odf_plan_t *plan, int64_t ticket, odf_stats *out);
+
+/* Block until the ticket is final or timeout_s elapses (then ODF_OK with
+ * out->state still PENDING or RUNNING). */
+odf_status odf_wait(odf_plan_t *plan, int64_t ticket, double timeout_s, odf_stats *out);
+
+/* Drain the request loop, free device memory owned by the plan.  NULL-safe;
+ * a second call on the same pointer is not allowed (the plan is freed). */
+odf_status odf_plan_destroy(odf_plan_t *plan);
+
+/* Number of fine-grid points N of a layout (App. E grid formula), or -1. */
+int64_t odf_grid_points(const odf_layout *layout);
+
+/* Workspace bytes that one point occupies while it is being processed. */
+int64_t odf_point_footprint(const odf_plan_t *plan);
+
+/* Workspace bytes the request loop reserves for a request of n_points. */
+int64_t odf_request_footprint(const odf_plan_t *plan, int32_t n_points);
+
+/* Message of the last error on this thread ("" if none). */
+const char *odf_last_error(void);
+
+/* ---- stage entry points, for checking each kernel on its own ---------- */
+
+/* Line-strength stage for point `point` of req: pre-selection, strength,
+ * damping and window of every line (Sec. 2.1 eq. l_nu_line; Sec. 4.3; App. E).
+ * Host outputs, each of capacity plan line count, in wavelength order of
+ * survivors: orig_index (index into the caller's line list), j_lo, j_hi,
+ * S [cm^2/g], a, b (= dnu_D/nu_0).  *n_surv receives the survivor count;
+ * *voigt_samples the sum of window lengths. */
+odf_status odf_stage_lines(odf_plan_t *plan, const odf_request *req, int32_t point,
+                           int64_t *n_surv, int64_t *voigt_samples,
+                           int64_t *orig_index, int32_t *j_lo, int32_t *j_hi,
+                           double *S, double *a, double *b);
+
+/* Line opacity on the fine grid for point `point` (before the floor):
+ * kappa_dev is a device buffer of N doubles (FP64 plan) or floats (MIXED). */
+odf_status odf_stage_fine(odf_plan_t *plan, const odf_request *req, int32_t point,
+                          void *kappa_dev);
+
+/* ODF reduction of one fine grid (floor, per-bin sort, sub-bin means):
+ * kappa_dev device [N] (double for FP64 plans, float for MIXED), out_dev
+ * device [n_bins][n_steps] (same type).  Runs on options.stream and waits. */
+odf_status odf_stage_reduce(odf_plan_t *plan, const void *kappa_dev, void *out_dev);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ODF_H */
