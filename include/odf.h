@@ -222,6 +222,11 @@ odf_status odf_stage_fine(odf_plan_t *plan, const odf_request *req, int32_t poin
  * device [n_bins][n_steps] (same type).  Runs on options.stream and waits. */
 odf_status odf_stage_reduce(odf_plan_t *plan, const void *kappa_dev, void *out_dev);
 
+/* Test hook for failure handling: the next batch of `ticket` that the
+ * request loop launches reports a launch error instead of running, so the
+ * ticket ends FAILED while every other ticket completes normally. */
+odf_status odf_debug_fail_next_batch(odf_plan_t *plan, int64_t ticket);
+
 #ifdef __cplusplus
 }
 #endif

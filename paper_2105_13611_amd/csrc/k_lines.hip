@@ -1,0 +1,332 @@
+// Line-list preparation, per-point state, line pre-selection and survivor
+// compaction (gfx950).
+//
+// Physics (Witzke et al. 2021):
+//  - Saha-Boltzmann stage populations N_k/U_k per gram with the electron
+//    density fixed by P_e = pe_over_p * P (Sec. 2.1; App. A; App. E first
+//    stage item i).
+//  - Doppler width dnu_D = (nu0/c) sqrt(2kT/m + v_turb^2) (App. E).
+//  - Line strength S of ell_nu = S H(x, a) from eq. l_nu_line (Sec. 2.1),
+//    damping parameter a = gamma / (4 pi dnu_D).
+//  - Pre-selection: keep a line when its core opacity S H(0, a) reaches
+//    cutoff * kappa_c(lambda0) (Sec. 4.3; App. E selection conditions).
+//  - Window: half-width where the Gaussian and Lorentz envelopes of the
+//    profile fall to half the cut, capped in Doppler widths.
+// All of this is FP64: the Boltzmann and Saha factors span more than the
+// FP32 range at the cool end of the grid.
+#include "odf_internal.h"
+
+namespace odf {
+
+__global__ void k_prep_lines(int64_t n, const double* __restrict__ lam_nm,
+                             const double* __restrict__ log_gf, const double* __restrict__ e_ev,
+                             const double* __restrict__ lg_rad, const double* __restrict__ lg_stark,
+                             const double* __restrict__ lg_vdw, const int32_t* __restrict__ species,
+                             const int32_t* __restrict__ stage, int32_t n_stages,
+                             double lambda_first_nm, double lnq, double cutoff, double kc_ref,
+                             double kc_lref, double kc_pow, double* j0s, double* amp, double* e_k,
+                             double* hc_k, double* g_rad, double* g_stark, double* g_vdw,
+                             double* thr, int32_t* ss) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double lam = lam_nm[i];
+  const double nu0 = kC / (lam * 1e-7);
+  const double pi_e2_mc = kPi * kEcharge * kEcharge / (kMe * kC);
+  j0s[i] = log(lam / lambda_first_nm) / lnq;
+  amp[i] = pi_e2_mc * exp10(log_gf[i]) / (kSqrtPi * nu0);
+  e_k[i] = e_ev[i] * kEv / kK;
+  hc_k[i] = kH * kC / kK * 1e7 / lam;
+  const double four_pi_nu0 = 4.0 * kPi * nu0;
+  g_rad[i] = exp10(lg_rad[i]) / four_pi_nu0;
+  g_stark[i] = exp10(lg_stark[i]) / four_pi_nu0;
+  g_vdw[i] = exp10(lg_vdw[i]) / four_pi_nu0;
+  thr[i] = cutoff * kc_ref * pow(lam / kc_lref, kc_pow);
+  ss[i] = species[i] * n_stages + stage[i];
+}
+
+hipError_t launch_prep_lines(hipStream_t st, int64_t n, const double* lam_nm, const double* log_gf,
+                             const double* e_ev, const double* lg_rad, const double* lg_stark,
+                             const double* lg_vdw, const int32_t* species, const int32_t* stage,
+                             int32_t n_stages, double lambda_first_nm, double lnq, double cutoff,
+                             double kc_ref, double kc_lref, double kc_pow, double* j0s, double* amp,
+                             double* e_k, double* hc_k, double* g_rad, double* g_stark,
+                             double* g_vdw, double* thr, int32_t* ss) {
+  if (n == 0) return hipSuccess;
+  const int64_t nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_prep_lines, dim3((unsigned)nb), dim3(256), 0, st, n, lam_nm, log_gf, e_ev,
+                     lg_rad, lg_stark, lg_vdw, species, stage, n_stages, lambda_first_nm, lnq,
+                     cutoff, kc_ref, kc_lref, kc_pow, j0s, amp, e_k, hc_k, g_rad, g_stark, g_vdw,
+                     thr, ss);
+  return hipGetLastError();
+}
+
+// One workgroup per point: gas state, Saha stage fractions (log space),
+// populations N_k/(U_k rho) and the thermal-plus-turbulent b = dnu_D/nu0.
+__global__ void k_point_state(Params P, Batch B) {
+  const int p = blockIdx.x;
+  const double T = B.T[p];
+  const double Pg = exp10(B.log10P[p]);
+  const double kT = kK * T;
+  const double pe = P.pe_over_p * Pg;
+  const double n_e = pe / kT;
+  const double n_heavy = (Pg - pe) / kT;
+  const int S = P.n_species, K = P.n_stages;
+  // sums over species in a fixed order (thread-independent, deterministic)
+  double sumA = 0.0, sumAM = 0.0;
+  for (int s = 0; s < S; ++s) {
+    sumA += B.abundance[s];
+    sumAM += B.abundance[s] * P.mass_amu[s];
+  }
+  const double n_H = n_heavy / (1.0 + sumA);
+  const double rho = n_H * kAmu * (kMassH + sumAM);
+  if (threadIdx.x == 0) {
+    const double t4 = T / 1.0e4;
+    PointState ps;
+    ps.T = T;
+    ps.cS = n_e * pow(t4, 1.0 / 6.0);
+    ps.cW = n_heavy * pow(t4, 0.3);
+    ps.n_e = n_e;
+    ps.n_heavy = n_heavy;
+    ps.n_H = n_H;
+    ps.rho = rho;
+    ps.pad = 0.0;
+    B.state[p] = ps;
+  }
+  const double saha = pow(2.0 * kPi * kMe * kK / (kH * kH), 1.5);
+  const double vt = B.vt_kms[p] * 1e5;
+  for (int s = threadIdx.x; s < S; s += blockDim.x) {
+    double logf[8];
+    logf[0] = 0.0;
+    double mx = 0.0;
+    for (int k = 0; k + 1 < K; ++k) {
+      const double ln_r = log(2.0) + log(P.part_fn[s * K + k + 1]) - log(P.part_fn[s * K + k]) +
+                          log(saha) + 1.5 * log(T) - P.chi_ev[s * (K - 1) + k] * kEv / kT -
+                          log(n_e);
+      logf[k + 1] = logf[k] + ln_r;
+      mx = fmax(mx, logf[k + 1]);
+    }
+    double z = 0.0;
+    for (int k = 0; k < K; ++k) z += exp(logf[k] - mx);
+    const double lse = mx + log(z);
+    for (int k = 0; k < K; ++k) {
+      const double f = exp(logf[k] - lse);
+      B.pop[(int64_t)p * S * K + s * K + k] =
+          B.abundance[s] * n_H * f / (P.part_fn[s * K + k] * rho);
+    }
+    const double m = P.mass_amu[s] * kAmu;
+    B.bT[(int64_t)p * S + s] = sqrt(2.0 * kT / m + vt * vt) / kC;
+  }
+}
+
+hipError_t launch_point_state(hipStream_t st, const Params& P, const Batch& B) {
+  if (B.n_points == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_point_state, dim3(B.n_points), dim3(64), 0, st, P, B);
+  return hipGetLastError();
+}
+
+struct LineEval {
+  double S, a, b;
+  int32_t jlo, jhi;
+  bool surv;
+};
+
+// Strength, damping, selection and window of sorted line i at one point.
+__device__ __forceinline__ LineEval eval_line(const Params& P, const DevLines& L, int64_t i,
+                                              const PointState& ps, const double* __restrict__ pop,
+                                              const double* __restrict__ bT) {
+  LineEval e;
+  const double T = ps.T;
+  const double b = bT[L.sp[i]];
+  const double stim = -expm1(-L.hc_k[i] / T);
+  const double boltz = exp(-L.e_k[i] / T);
+  const double S = L.amp[i] * pop[L.ss[i]] * boltz * stim / b;
+  const double a = (L.g_rad[i] + L.g_stark[i] * ps.cS + L.g_vdw[i] * ps.cW) / b;
+  const double thr = L.thr[i];
+  e.S = S;
+  e.a = a;
+  e.b = b;
+  e.surv = false;
+  e.jlo = 0;
+  e.jhi = -1;
+  if (!(S * erfcx(a) >= thr)) return e;
+  const double xg = sqrt(fmax(0.0, log(2.0 * S / thr)));
+  const double xl = sqrt(2.0 * S * a / (kSqrtPi * thr));
+  const double xw = fmin(P.cap, fmax(xg, xl));
+  const double j0 = L.j0s[i];
+  const double lo = ceil(j0 - log1p(xw * b) / P.lnq);
+  const double hi = floor(j0 - log1p(-xw * b) / P.lnq);
+  const double jl = fmax(lo, 0.0);
+  const double jh = fmin(hi, (double)(P.N - 1));
+  if (jl > jh) return e;
+  e.jlo = (int32_t)jl;
+  e.jhi = (int32_t)jh;
+  e.surv = true;
+  return e;
+}
+
+__global__ __launch_bounds__(kLineBlock) void k_select(Params P, DevLines L, Batch B) {
+  const int p = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * kLineBlock + threadIdx.x;
+  const int64_t nblk = gridDim.x;
+  const PointState ps = B.state[p];
+  bool s = false;
+  if (i < L.n) {
+    s = eval_line(P, L, i, ps, B.pop + (int64_t)p * P.n_species * P.n_stages,
+                  B.bT + (int64_t)p * P.n_species).surv;
+    B.flags[(int64_t)p * B.rec_stride + i] = s ? 1 : 0;
+  }
+  const int cnt = __syncthreads_count(s);
+  if (threadIdx.x == 0) B.blk[(int64_t)p * nblk + blockIdx.x] = cnt;
+}
+
+hipError_t launch_select(hipStream_t st, const Params& P, const DevLines& L, const Batch& B) {
+  if (B.n_points == 0 || L.n == 0) return hipSuccess;
+  const int64_t nblk = n_line_blocks(L.n);
+  hipLaunchKernelGGL(k_select, dim3((unsigned)nblk, B.n_points), dim3(kLineBlock), 0, st, P, L, B);
+  return hipGetLastError();
+}
+
+// Exclusive scan of the per-block survivor counts of one point (one
+// workgroup of 1024 threads per point, fixed order: deterministic).
+__global__ __launch_bounds__(1024) void k_scan(Batch B, int64_t nblk) {
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t carry;
+  const int p = blockIdx.x;
+  int32_t* c = B.blk + (int64_t)p * nblk;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nblk; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int32_t v = (i < nblk) ? c[i] : 0;
+    int32_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t t = __shfl_up(x, o, 64);
+      if (lane >= o) x += t;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t run = 0;
+      for (int w = 0; w < 16; ++w) {
+        const int32_t t = wsum[w];
+        wsum[w] = run;
+        run += t;
+      }
+    }
+    __syncthreads();
+    const int32_t excl = carry + wsum[wid] + x - v;
+    if (i < nblk) c[i] = excl;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = excl + v;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    B.nsurv[p] = carry;
+    B.hmax[p] = 0;
+    B.nsamp[p] = 0ull;
+  }
+}
+
+hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const Batch& B) {
+  (void)P;
+  if (B.n_points == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan, dim3(B.n_points), dim3(1024), 0, st, B, n_line_blocks(L.n));
+  return hipGetLastError();
+}
+
+// Survivor emission: the intra-block prefix of the flags gives each kept
+// line its slot after the block's offset, so the survivor list keeps the
+// wavelength order (stable compaction, no atomics on positions).
+template <bool kRec64>
+__global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch B) {
+  __shared__ int32_t wcnt[kLineBlock / 64];
+  __shared__ int32_t red_h[kLineBlock / 64];
+  __shared__ unsigned long long red_n[kLineBlock / 64];
+  const int p = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * kLineBlock + threadIdx.x;
+  const int64_t nblk = gridDim.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const bool f = (i < L.n) && B.flags[(int64_t)p * B.rec_stride + i];
+  const unsigned long long m = __ballot(f);
+  if (lane == 0) wcnt[wid] = __popcll(m);
+  __syncthreads();
+  int32_t off = B.blk[(int64_t)p * nblk + blockIdx.x];
+  for (int w = 0; w < wid; ++w) off += wcnt[w];
+  const unsigned long long below = (lane == 0) ? 0ull : (m & (~0ull >> (64 - lane)));
+  off += __popcll(below);
+  int32_t half = 0;
+  unsigned long long ns = 0;
+  if (f) {
+    const PointState ps = B.state[p];
+    const LineEval e = eval_line(P, L, i, ps, B.pop + (int64_t)p * P.n_species * P.n_stages,
+                                 B.bT + (int64_t)p * P.n_species);
+    const double j0 = L.j0s[i];
+    const double Jd = rint(j0);
+    const int32_t J = (int32_t)Jd;
+    const int64_t slot = (int64_t)p * B.rec_stride + off;
+    if (kRec64) {
+      Rec64 r;
+      r.J = J;
+      r.jlo = e.jlo;
+      r.jhi = e.jhi;
+      r.li = (int32_t)i;
+      r.phi = j0 - Jd;
+      r.S = e.S;
+      r.y = e.a;
+      r.c1 = P.lnq / e.b;
+      reinterpret_cast<Rec64*>(B.rec)[slot] = r;
+    } else {
+      Rec32 r;
+      r.J = J;
+      r.jlo = e.jlo;
+      r.jhi = e.jhi;
+      r.li = (int32_t)i;
+      r.phi = (float)(j0 - Jd);
+      r.S = (float)e.S;
+      r.y = (float)e.a;
+      r.c1 = (float)(P.lnq / e.b);
+      reinterpret_cast<Rec32*>(B.rec)[slot] = r;
+    }
+    B.win[slot] = make_int2(e.jlo, e.jhi);
+    half = max(J - e.jlo, e.jhi - J) + 1;
+    ns = (unsigned long long)(e.jhi - e.jlo + 1);
+  }
+  // block reductions, then one atomic per block (integers: order-free)
+  for (int o = 32; o > 0; o >>= 1) {
+    half = max(half, __shfl_xor(half, o, 64));
+    ns += __shfl_xor(ns, o, 64);
+  }
+  if (lane == 0) {
+    red_h[wid] = half;
+    red_n[wid] = ns;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t h = 0;
+    unsigned long long n = 0;
+    for (int w = 0; w < kLineBlock / 64; ++w) {
+      h = max(h, red_h[w]);
+      n += red_n[w];
+    }
+    if (n) {
+      atomicMax(B.hmax + p, h);
+      atomicAdd(B.nsamp + p, n);
+    }
+  }
+}
+
+hipError_t launch_emit(hipStream_t st, const Params& P, const DevLines& L, const Batch& B,
+                       int rec64) {
+  if (B.n_points == 0 || L.n == 0) return hipSuccess;
+  const int64_t nblk = n_line_blocks(L.n);
+  if (rec64)
+    hipLaunchKernelGGL(k_emit<true>, dim3((unsigned)nblk, B.n_points), dim3(kLineBlock), 0, st, P,
+                       L, B);
+  else
+    hipLaunchKernelGGL(k_emit<false>, dim3((unsigned)nblk, B.n_points), dim3(kLineBlock), 0, st,
+                       P, L, B);
+  return hipGetLastError();
+}
+
+}  // namespace odf

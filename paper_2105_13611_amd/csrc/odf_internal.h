@@ -1,0 +1,158 @@
+// Internal layout shared by the host runtime and the gfx950 kernels of the
+// ODF engine.  Nothing here is part of the public C ABI (include/odf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace odf {
+
+// ---- physical constants, CGS (CODATA 2018) --------------------------------
+constexpr double kC = 2.99792458e10;           // cm/s
+constexpr double kH = 6.62607015e-27;          // erg s
+constexpr double kK = 1.380649e-16;            // erg/K
+constexpr double kEcharge = 4.803204712570263e-10;  // statC
+constexpr double kMe = 9.1093837015e-28;       // g
+constexpr double kAmu = 1.66053906660e-24;     // g
+constexpr double kEv = 1.602176634e-12;        // erg
+constexpr double kMassH = 1.008;               // amu
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtPi = 1.77245385090551602730;
+
+// ---- tiling of the Voigt scatter-sum --------------------------------------
+constexpr int kWave = 64;
+constexpr int kRows = 16;                        // rows of 64 points per wave
+constexpr int kWavePoints = kWave * kRows;       // 1024 fine points per wave
+constexpr int kWavesPerWG = 4;
+constexpr int kWGPoints = kWavePoints * kWavesPerWG;  // 4096 per workgroup
+constexpr int kLineBlock = 256;                  // lines per workgroup in K1
+
+// ---- Voigt region constants -----------------------------------------------
+// FP32: |z| >= 15 two-node Gauss-Hermite pair, 6 <= |z| < 15 four-node,
+// |z| < 6 pole-corrected trapezoidal rule (h = 0.7, nodes |t| <= 4.5).
+constexpr float kFarR32 = 15.0f;
+constexpr float kRingR32 = 6.0f;
+constexpr int kTrap32Half = 7;                   // k = -7..7
+constexpr float kTrap32H = 0.7f;
+constexpr float kTrap32Tmax = 4.5f;
+// FP64: |z| >= 10 eight-node Gauss-Hermite pair sum, else trapezoid h=0.5, |t|<=6
+constexpr double kFarR64 = 10.0;
+constexpr int kTrap64Half = 12;                  // k = -12..12
+constexpr double kTrap64H = 0.5;
+constexpr double kTrap64Tmax = 6.0;
+
+// Quadrature constants computed on the host at plan time.
+struct QuadConsts {
+  float gh2_t2;            // t^2 of the 2-node rule (positive node)
+  float gh4_t2[2];         // t_k^2 of the 4-node rule, k = 1, 2
+  float gh4_w[2];          // omega_k / pi
+  float tr32_ci[2 * kTrap32Half + 1];   // (h/pi) e^{-t^2}, t = k h
+  float tr32_ch[2 * kTrap32Half + 1];   // (h/pi) e^{-t^2}, t = (k + 1/2) h
+  double gh8_t2[4];        // t_k^2 of the 8-node rule
+  double gh8_w[4];         // omega_k / pi
+  double tr64_ci[2 * kTrap64Half + 1];
+  double tr64_ch[2 * kTrap64Half + 1];
+};
+
+// ---- resident line list (sorted by wavelength), structure of arrays --------
+struct DevLines {
+  int64_t n;
+  const double* j0s;     // fractional fine-grid index of the line centre
+  const double* amp;     // (pi e^2 / m_e c) g f / (sqrt(pi) nu0)
+  const double* e_k;     // E_low / k  [K]
+  const double* hc_k;    // h nu0 / k  [K]
+  const double* g_rad;   // gamma_rad   / (4 pi nu0)
+  const double* g_stark; // gamma_stark / (4 pi nu0)
+  const double* g_vdw;   // gamma_vdW   / (4 pi nu0)
+  const double* thr;     // cutoff * kappa_c(lambda0)
+  const int32_t* sp;     // species
+  const int32_t* ss;     // species * n_stages + stage
+};
+
+// Per-point state computed on the device.
+struct PointState {
+  double T;
+  double cS;        // n_e (T/1e4)^(1/6)
+  double cW;        // N_heavy (T/1e4)^0.3
+  double n_e, n_heavy, n_H, rho;
+  double pad;
+};
+
+// Survivor records.  `win` (j_lo, j_hi) is kept apart for the wave-wide
+// intersection test; the record is read once per intersecting line.
+struct alignas(16) Rec32 {
+  int32_t J;        // nearest integer of the fractional centre index
+  int32_t jlo, jhi; // window, clipped to the grid
+  int32_t li;       // sorted line index
+  float phi;        // fractional centre minus J, in [-1/2, 1/2]
+  float S;          // line strength [cm^2/g]
+  float y;          // damping parameter a
+  float c1;         // ln q / b
+};
+struct alignas(16) Rec64 {
+  int32_t J, jlo, jhi, li;
+  double phi, S, y, c1;
+};
+
+struct Batch {
+  // all pointers are into the workspace; strides per point
+  int32_t n_points;
+  const double* T;      // [B]
+  const double* log10P; // [B]
+  const double* vt_kms; // [B]
+  const double* abundance;  // [S]
+  PointState* state;    // [B]
+  double* pop;          // [B][S*K]
+  double* bT;           // [B][S]
+  uint8_t* flags;       // [B][L]
+  int32_t* blk;         // [B][nblk]   counts, then offsets
+  int32_t* nsurv;       // [B]
+  int32_t* hmax;        // [B]         max half-window in fine points
+  unsigned long long* nsamp;  // [B]
+  void* rec;            // [B][L] Rec32 or Rec64
+  int2* win;            // [B][L]
+  void* kappa;          // [B][N] float or double
+  int64_t rec_stride;   // = L
+  int64_t kappa_stride; // = N
+};
+
+struct Params {
+  int32_t n_species, n_stages;
+  const double* mass_amu;  // device [S]
+  const double* chi_ev;    // device [S][K-1]
+  const double* part_fn;   // device [S][K]
+  double pe_over_p;
+  double cutoff, cap;
+  double lnq;              // ln(1 + 1/R), FP64
+  double lambda_first_nm;
+  double kc_ref, kc_lref, kc_power;   // kappa_c = kc_ref (lambda / kc_lref)^kc_power
+  int64_t N;
+  int32_t n_bins, n_steps;
+  const int64_t* edges;    // device [n_bins+1]
+  const double* Fcum;      // device [n_steps+1] cumulative fractions, F[0]=0, F[n]=1
+  int32_t mean;            // 0 geometric, 1 arithmetic
+  int32_t precision;       // 0 fp64, 1 mixed
+};
+
+// ---- launchers (defined in the .hip files) ---------------------------------
+hipError_t launch_prep_lines(hipStream_t st, int64_t n, const double* lam_nm, const double* log_gf,
+                             const double* e_ev, const double* lg_rad, const double* lg_stark,
+                             const double* lg_vdw, const int32_t* species, const int32_t* stage,
+                             int32_t n_stages, double lambda_first_nm, double lnq, double cutoff,
+                             double kc_ref, double kc_lref, double kc_pow,
+                             double* j0s, double* amp, double* e_k, double* hc_k, double* g_rad,
+                             double* g_stark, double* g_vdw, double* thr, int32_t* ss);
+hipError_t launch_point_state(hipStream_t st, const Params& P, const Batch& B);
+hipError_t launch_select(hipStream_t st, const Params& P, const DevLines& L, const Batch& B);
+hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const Batch& B);
+hipError_t launch_emit(hipStream_t st, const Params& P, const DevLines& L, const Batch& B, int rec64);
+hipError_t launch_voigt(hipStream_t st, const Params& P, const Batch& B, const QuadConsts& Q);
+hipError_t launch_odf(hipStream_t st, const Params& P, const void* kappa, int64_t kappa_stride,
+                      int32_t n_points, void* out, int max_bin, void* gscratch,
+                      const int64_t* goff, int64_t gscratch_stride);
+// largest bin (in points) that the ODF kernel sorts in LDS
+inline int odf_lds_cap(int precision) { return (128 * 1024) / (precision == 1 ? 4 : 8); }
+
+inline int64_t n_line_blocks(int64_t n) { return (n + kLineBlock - 1) / kLineBlock; }
+
+}  // namespace odf

@@ -1,0 +1,66 @@
+// Host-side plan object of the ODF engine (private).
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdarg>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/odf.h"
+#include "odf_internal.h"
+
+namespace odf {
+
+QuadConsts make_quad_consts();
+void set_error(const char* fmt, ...);
+std::string g_last_error_copy();
+void g_last_error_clear();
+
+// Layout of one batch slot inside the workspace.
+struct SlotLayout {
+  int64_t off_T, off_logP, off_vt, off_abund, off_state, off_pop, off_bT, off_flags, off_blk,
+      off_nsurv, off_hmax, off_nsamp, off_rec, off_win, off_kappa, off_gscr;
+  int64_t bytes;      // total bytes of the slot
+  int32_t points;     // points per slot
+};
+
+struct Request;       // request-loop entry (loop.cpp)
+class RequestLoop;    // (loop.cpp)
+
+}  // namespace odf
+
+struct odf_plan_s {
+  // validated copies
+  odf_options opts{};
+  int32_t n_species = 0, n_stages = 0;
+  int64_t n_lines = 0, N = 0;
+  int32_t n_bins = 0, n_steps = 0;
+  int32_t max_bin = 0;
+  double lambda_first_nm = 0, lambda_last_nm = 0, resolving_power = 0, lnq = 0;
+  std::vector<int64_t> edges;
+  std::vector<double> Fcum;
+  std::vector<int64_t> orig;        // sorted position -> caller's line index
+
+  // device allocations owned by the plan
+  std::vector<void*> owned;
+  odf::DevLines lines{};
+  odf::Params params{};
+  odf::QuadConsts quad{};
+  int64_t* d_goff = nullptr;        // per-bin offsets into the ODF global scratch
+  int64_t gscr_elems = 0;           // scratch elements per point
+
+  // workspace carving
+  int64_t per_point_bytes = 0;
+  int64_t fixed_bytes = 0;
+  int32_t compute_points = 0;       // points per odf_compute batch
+  odf::SlotLayout compute_slot{};
+
+  std::mutex compute_mu;
+  std::unique_ptr<odf::RequestLoop> loop;
+};

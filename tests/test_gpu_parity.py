@@ -1,0 +1,232 @@
+"""Parity of the HIP path with the FP64 oracle, stage by stage and end to end.
+
+Tolerances: FP64 plain path <= 1e-9 relative per ODF step; mixed path
+<= 1e-3 relative per step (max |dlog10 kappa| printed).  Kernel stages:
+line strengths 1e-12, fine-grid opacity 1e-10 (FP64) / 2e-4 (FP32, relative
+to max(kappa, floor)), ODF reduction of a given grid 1e-12 / 1e-6.
+"""
+import math
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_13611_amd import workload as W
+from tests.gpu_helpers import (ambiguous_bins, ambiguous_lines, ambiguous_points, floor_values,
+                               log10_err, rel_err)
+
+pytestmark = pytest.mark.gpu
+
+TOL_STEP = {"fp64": 1e-9, "mixed": 1e-3}
+TOL_FINE = {"fp64": 1e-10, "mixed": 2e-4}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def odf(torch):
+    from paper_2105_13611_amd import odf as o
+    o.load_library()
+    return o
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return W.config(1)
+
+
+@pytest.fixture(scope="module")
+def plans1(odf, cfg1):
+    ps = {p: odf.plan_for(cfg1, precision=p, workspace_bytes=256 << 20) for p in ("fp64", "mixed")}
+    yield ps
+    for p in ps.values():
+        p.destroy()
+
+
+def _lq(w, i=0, abundance=None):
+    a = w.species.abundance if abundance is None else abundance
+    return oracle.line_quantities(w.lines, w.species, a, float(w.points.T_K[i]), float(w.points.log10_P[i]),
+                                  float(w.points.vturb_kms[i]), w.layout, w.options)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_k1_line_strengths(plans1, cfg1, prec):
+    w = cfg1
+    res = plans1[prec].stage_lines(w.species.abundance, w.points, 0)
+    lq = _lq(w)
+    keep_tie, lo_tie, hi_tie = ambiguous_lines(lq)
+    so = set(np.nonzero(lq["surv"])[0].tolist())
+    sg = set(res["orig"].tolist())
+    for i in so ^ sg:
+        assert keep_tie[i] or lo_tie[i] or hi_tie[i], f"line {i} kept differently without a near-tie"
+    # survivors come out in wavelength order
+    assert np.all(np.diff(w.lines.lambda_nm[res["orig"]]) >= 0)
+    idx = res["orig"]
+    m = np.array([i in so for i in idx])
+    o = idx[m]
+    np.testing.assert_allclose(res["S"][m], lq["S"][o], rtol=1e-12)
+    np.testing.assert_allclose(res["a"][m], lq["a"][o], rtol=1e-12)
+    np.testing.assert_allclose(res["b"][m], lq["b"][o], rtol=1e-13)
+    ok_lo = (res["jlo"][m] == lq["jlo"][o]) | lo_tie[o]
+    ok_hi = (res["jhi"][m] == lq["jhi"][o]) | hi_tie[o]
+    assert ok_lo.all() and ok_hi.all()
+    if not (keep_tie.any() or lo_tie.any() or hi_tie.any()):
+        assert res["voigt_samples"] == int(np.sum(lq["jhi"][lq["surv"]] - lq["jlo"][lq["surv"]] + 1))
+        assert res["n_surv"] == len(so)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_k3_fine_grid(plans1, cfg1, prec):
+    w = cfg1
+    lq = _lq(w)
+    N = lq["N"]
+    kap = plans1[prec].stage_fine(w.species.abundance, w.points, 0).double().cpu().numpy()
+    ref = oracle.fine_opacity(lq, w.layout, 0, N)
+    fl = floor_values(w.layout, w.options, 0, N)
+    err = np.abs(kap - ref) / np.maximum(ref, fl)
+    amb = ambiguous_points(lq, N)
+    err[amb] = 0.0
+    print(f"{prec}: fine-grid max err {err.max():.3e}, ambiguous points {amb.size}")
+    assert err.max() <= TOL_FINE[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("mean", ["geometric", "arithmetic"])
+def test_k4_reduce_given_grid(odf, cfg1, torch, prec, mean):
+    w = cfg1
+    w2 = replace(w, options=replace(w.options, mean=mean))
+    lq = _lq(w2)
+    N = lq["N"]
+    ref_fine = oracle.fine_opacity(lq, w.layout, 0, N)
+    if prec == "mixed":
+        ref_fine = ref_fine.astype(np.float32).astype(np.float64)
+    with odf.plan_for(w2, precision=prec, workspace_bytes=128 << 20) as plan:
+        out = plan.stage_reduce(torch.from_numpy(ref_fine)).double().cpu().numpy()
+    fl = floor_values(w.layout, w.options, 0, N)
+    if prec == "mixed":
+        fl = fl.astype(np.float32).astype(np.float64)
+    e = w.layout.bin_edges
+    for b in range(len(e) - 1):
+        kt = np.maximum(ref_fine[e[b]:e[b + 1]], fl[e[b]:e[b + 1]])
+        r = oracle.odf_reduce_bin(kt, w.layout.step_frac, mean)
+        np.testing.assert_allclose(out[b], r, rtol=1e-12 if prec == "fp64" else 1e-6)
+
+
+def _compare_points(w, out, prec, bins=None, abundance=None):
+    a = w.species.abundance if abundance is None else abundance
+    worst, worst_log, skipped = 0.0, 0.0, 0
+    for i in range(w.points.n_points):
+        ref, _, ex = oracle.odf_point(w.lines, w.species, a, float(w.points.T_K[i]),
+                                      float(w.points.log10_P[i]), float(w.points.vturb_kms[i]),
+                                      w.layout, w.options, bins)
+        bsel = np.arange(w.layout.n_bins) if bins is None else np.asarray(bins)
+        amb = ambiguous_bins(ex["lq"], w.layout.bin_edges)
+        got = out[i][bsel]
+        for k, b in enumerate(bsel):
+            if int(b) in amb:
+                skipped += 1
+                continue
+            worst = max(worst, float(rel_err(got[k], ref[k]).max()))
+            worst_log = max(worst_log, float(log10_err(got[k], ref[k]).max()))
+    return worst, worst_log, skipped
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_end_to_end_cfg1(plans1, cfg1, prec):
+    w = cfg1
+    out, st = plans1[prec].compute(w.species.abundance, w.points)
+    out = out.double().cpu().numpy()
+    worst, worst_log, skipped = _compare_points(w, out, prec)
+    print(f"cfg1 {prec}: max rel err per step {worst:.3e}, max |dlog10 k| {worst_log:.3e}, "
+          f"ambiguous bins skipped {skipped}; stats {st}")
+    assert skipped <= 1
+    assert worst <= TOL_STEP[prec]
+    _, cnt, _ = oracle.odf_point(w.lines, w.species, w.species.abundance, 5000.0, 4.0, 2.0, w.layout,
+                                 w.options, bins=[0])
+    assert st["line_evals"] == cnt["line_evals"]
+    assert abs(st["survivors"] - cnt["survivors"]) <= 1
+    assert st["state"] == "DONE" and st["points"] == 1
+
+
+@pytest.fixture(scope="module")
+def multi():
+    """Several tiles with a ragged tail, several points spanning the T-P grid."""
+    w = W.config(2, n_lines=20_000, lam_range=(300.0, 345.0), n_bins=7)
+    pts = W.Points(np.array([2000.0, 5000.0, 20000.0, 200000.0, 3000.0, 9000.0]),
+                   np.array([-4.0, 4.0, 8.0, 0.0, 6.0, 2.0]),
+                   np.array([2.0, 0.0, 8.0, 1.0, 4.0, 2.0]))
+    return replace(w, points=pts)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_end_to_end_multi_tile_multi_point(odf, multi, prec):
+    w = multi
+    assert W.grid_size(300.0, 345.0, 5e5) % 4096 != 0
+    # a small workspace forces several device batches
+    with odf.plan_for(w, precision=prec, workspace_bytes=24 << 20) as plan:
+        out, st = plan.compute(w.species.abundance, w.points)
+        out = out.double().cpu().numpy()
+    worst, worst_log, skipped = _compare_points(w, out, prec)
+    print(f"multi {prec}: max rel err {worst:.3e}, max |dlog10 k| {worst_log:.3e}, skipped {skipped}")
+    assert skipped <= 2
+    assert worst <= TOL_STEP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_deterministic(plans1, cfg1, prec):
+    w = cfg1
+    a, _ = plans1[prec].compute(w.species.abundance, w.points)
+    b, _ = plans1[prec].compute(w.species.abundance, w.points)
+    assert bool((a == b).all())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_edge_layout_tiny_and_huge_bins(odf, prec):
+    # bins of 1, 1, 3 and 20000 points (the FP64 path sorts the last one in
+    # global scratch), plus a ragged remainder; arithmetic mean
+    lf, ll = 300.0, 315.5
+    N = W.grid_size(lf, ll, 5e5)
+    edges = np.array([0, 1, 2, 5, 20005, N], dtype=np.int64)
+    base = W.config(1, n_lines=3000, lam_range=(lf, ll))
+    w = replace(base, layout=W.Layout(lf, ll, 5e5, edges, W.STEP_FRAC_12.copy()),
+                options=replace(base.options, mean="arithmetic"))
+    with odf.plan_for(w, precision=prec, workspace_bytes=64 << 20) as plan:
+        out, _ = plan.compute(w.species.abundance, w.points)
+        out = out.double().cpu().numpy()
+    worst, _, skipped = _compare_points(w, out, prec)
+    assert skipped == 0 and worst <= TOL_STEP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_degenerate_no_survivors_and_empty_list(odf, cfg1, prec):
+    w = cfg1
+    tiny = np.full(w.species.n_species, 1e-40)
+    with odf.plan_for(w, precision=prec, workspace_bytes=64 << 20) as plan:
+        out, st = plan.compute(tiny, w.points)
+        assert st["survivors"] == 0
+        worst, _, _ = _compare_points(w, out.double().cpu().numpy(), prec, abundance=tiny)
+        assert worst <= TOL_STEP[prec]
+    empty = replace(w, lines=w.lines.take(np.arange(0)))
+    with odf.plan_for(empty, precision=prec, workspace_bytes=64 << 20) as plan:
+        out, st = plan.compute(w.species.abundance, w.points)
+        got = out.double().cpu().numpy()[0]
+    fl = floor_values(w.layout, w.options, 0, int(w.layout.bin_edges[-1]))
+    e = w.layout.bin_edges
+    for b in range(len(e) - 1):
+        ref = oracle.odf_reduce_bin(fl[e[b]:e[b + 1]], w.layout.step_frac)
+        np.testing.assert_allclose(got[b], ref, rtol=TOL_STEP[prec])
+
+
+def test_options_cutoff_and_cap(odf, multi):
+    w = replace(multi, options=replace(multi.options, cutoff=1e-3, window_cap_doppler=50.0),
+                points=multi.points.take(np.array([1, 3])))
+    with odf.plan_for(w, precision="fp64", workspace_bytes=64 << 20) as plan:
+        out, _ = plan.compute(w.species.abundance, w.points)
+    worst, _, skipped = _compare_points(w, out.double().cpu().numpy(), "fp64")
+    assert skipped <= 1 and worst <= TOL_STEP["fp64"]
