@@ -114,7 +114,10 @@ typedef struct {
  *                     the request loop admits at once.
  *   stream            hipStream_t used by odf_compute (NULL = default stream).
  *   max_batch_points  upper bound on points per device batch (0 = automatic).
- *   loop_streams      streams used by the request loop (0 = 2). */
+ *   loop_streams      streams used by the request loop (0 = 2).
+ *   kernel_timing     nonzero: odf_compute brackets every kernel launch with
+ *                     HIP events on options.stream; totals are read with
+ *                     odf_stage_times(). */
 typedef struct {
   odf_precision precision;
   odf_mean mean;
@@ -127,6 +130,7 @@ typedef struct {
   void *stream;
   int32_t max_batch_points;
   int32_t loop_streams;
+  int32_t kernel_timing;
 } odf_options;
 
 /* One ODF request.
@@ -221,6 +225,13 @@ odf_status odf_stage_fine(odf_plan_t *plan, const odf_request *req, int32_t poin
  * kappa_dev device [N] (double for FP64 plans, float for MIXED), out_dev
  * device [n_bins][n_steps] (same type).  Runs on options.stream and waits. */
 odf_status odf_stage_reduce(odf_plan_t *plan, const void *kappa_dev, void *out_dev);
+
+/* Kernel times accumulated by odf_compute when options.kernel_timing is set,
+ * per stage: 0 point state, 1 line selection, 2 survivor scan, 3 survivor
+ * emission, 4 Voigt scatter-sum, 5 ODF reduction.  ms[6] receives the summed
+ * HIP-event durations in milliseconds, launches[6] the launch counts; reset
+ * nonzero clears the totals afterwards. */
+odf_status odf_stage_times(odf_plan_t *plan, double *ms, int64_t *launches, int32_t reset);
 
 /* Test hook for failure handling: the next batch of `ticket` that the
  * request loop launches reports a launch error instead of running, so the

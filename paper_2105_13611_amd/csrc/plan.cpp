@@ -230,17 +230,58 @@ Batch make_batch(const odf_plan_s* p, const SlotLayout& s, char* base, int32_t n
 
 // Enqueue the whole per-point chain for the points already staged in `B`:
 // state -> selection -> scan -> survivor emission -> Voigt -> ODF.
+namespace {
+
+// Records an event pair around one launch when timing is on.
+struct TimedLaunch {
+  StageTimer* t;
+  hipStream_t st;
+  size_t pair = 0;
+  TimedLaunch(StageTimer* timer, hipStream_t s, int stage) : t(timer), st(s) {
+    if (!t) return;
+    if (2 * (t->used + 1) > t->pool.size()) {
+      hipEvent_t a = nullptr, b = nullptr;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { t = nullptr; return; }
+      t->pool.push_back(a);
+      t->pool.push_back(b);
+      t->stage_of_pair.push_back(0);
+    }
+    pair = t->used++;
+    t->stage_of_pair[pair] = stage;
+    (void)hipEventRecord(t->pool[2 * pair], st);
+  }
+  ~TimedLaunch() {
+    if (t) (void)hipEventRecord(t->pool[2 * pair + 1], st);
+  }
+};
+
+}  // namespace
+
 odf_status enqueue_batch(odf_plan_s* p, const Batch& B, char* slot_base, const SlotLayout& s,
-                         void* out, hipStream_t st) {
-  HIP_TRY(launch_point_state(st, p->params, B));
-  HIP_TRY(launch_select(st, p->params, p->lines, B));
-  HIP_TRY(launch_scan(st, p->params, p->lines, B));
-  HIP_TRY(launch_emit(st, p->params, p->lines, B, p->opts.precision == ODF_PREC_FP64));
-  HIP_TRY(launch_voigt(st, p->params, B, p->quad));
-  if (out)
+                         void* out, hipStream_t st, StageTimer* timer) {
+  { TimedLaunch tl(timer, st, 0); HIP_TRY(launch_point_state(st, p->params, B)); }
+  { TimedLaunch tl(timer, st, 1); HIP_TRY(launch_select(st, p->params, p->lines, B)); }
+  { TimedLaunch tl(timer, st, 2); HIP_TRY(launch_scan(st, p->params, p->lines, B)); }
+  { TimedLaunch tl(timer, st, 3); HIP_TRY(launch_emit(st, p->params, p->lines, B, p->opts.precision == ODF_PREC_FP64)); }
+  { TimedLaunch tl(timer, st, 4); HIP_TRY(launch_voigt(st, p->params, B, p->quad)); }
+  if (out) {
+    TimedLaunch tl(timer, st, 5);
     HIP_TRY(launch_odf(st, p->params, B.kappa, B.kappa_stride, B.n_points, out, p->max_bin,
                        slot_base + s.off_gscr, p->d_goff, p->gscr_elems));
+  }
   return ODF_OK;
+}
+
+// After the stream has drained: add the recorded pairs to the totals.
+void collect_timer(StageTimer& t) {
+  for (size_t i = 0; i < t.used; ++i) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, t.pool[2 * i], t.pool[2 * i + 1]) == hipSuccess) {
+      t.ms[t.stage_of_pair[i]] += ms;
+      t.launches[t.stage_of_pair[i]] += 1;
+    }
+  }
+  t.used = 0;
 }
 
 odf_status validate_request(const odf_plan_s* p, const odf_request* r, bool need_out) {
@@ -466,10 +507,26 @@ odf_status odf_plan(const odf_lines* lines, const odf_species* species, const od
 
 int64_t odf_point_footprint(const odf_plan_t* plan) { return plan ? plan->per_point_bytes : -1; }
 
+odf_status odf_stage_times(odf_plan_t* plan, double* ms, int64_t* launches, int32_t reset) {
+  g_err.clear();
+  if (!plan || !ms || !launches) { set_error("odf_stage_times: NULL argument"); return ODF_E_INVALID; }
+  std::lock_guard<std::mutex> guard(plan->compute_mu);
+  for (int k = 0; k < kStages; ++k) {
+    ms[k] = plan->timer.ms[k];
+    launches[k] = plan->timer.launches[k];
+    if (reset) {
+      plan->timer.ms[k] = 0.0;
+      plan->timer.launches[k] = 0;
+    }
+  }
+  return ODF_OK;
+}
+
 odf_status odf_plan_destroy(odf_plan_t* plan) {
   if (!plan) return ODF_OK;
   plan->loop.reset();  // drains and joins the request loop
   (void)hipDeviceSynchronize();
+  for (hipEvent_t e : plan->timer.pool) (void)hipEventDestroy(e);
   free_owned(plan);
   delete plan;
   return ODF_OK;
@@ -498,11 +555,13 @@ odf_status odf_compute(odf_plan_t* p, const odf_request* r, odf_stats* stats) {
     HIP_TRY(hipMemcpyAsync(base + sl.off_vt, r->vturb_kms + b0, 8 * nb, hipMemcpyHostToDevice, s));
     Batch B = make_batch(p, sl, base, nb);
     char* outp = static_cast<char*>(r->out) + (size_t)b0 * p->n_bins * p->n_steps * osz;
-    if ((st = enqueue_batch(p, B, base, sl, outp, s)) != ODF_OK) return st;
+    if ((st = enqueue_batch(p, B, base, sl, outp, s, p->opts.kernel_timing ? &p->timer : nullptr)) != ODF_OK)
+      return st;
     HIP_TRY(hipMemcpyAsync(h_nsurv.data() + b0, B.nsurv, 4 * nb, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h_nsamp.data() + b0, B.nsamp, 8 * nb, hipMemcpyDeviceToHost, s));
   }
   HIP_TRY(hipStreamSynchronize(s));
+  if (p->opts.kernel_timing) collect_timer(p->timer);
   if (stats) {
     std::memset(stats, 0, sizeof *stats);
     stats->state = ODF_DONE;

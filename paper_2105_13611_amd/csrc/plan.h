@@ -30,6 +30,16 @@ struct SlotLayout {
   int32_t points;     // points per slot
 };
 
+// HIP-event timing of the kernels that odf_compute launches (opt-in).
+constexpr int kStages = 6;
+struct StageTimer {
+  std::vector<hipEvent_t> pool;      // event pairs, reused between calls
+  std::vector<int> stage_of_pair;    // stage of each recorded pair
+  size_t used = 0;                   // pairs recorded since the last collect
+  double ms[kStages] = {0, 0, 0, 0, 0, 0};
+  int64_t launches[kStages] = {0, 0, 0, 0, 0, 0};
+};
+
 struct Request;       // request-loop entry (loop.cpp)
 class RequestLoop;    // (loop.cpp)
 
@@ -61,6 +71,7 @@ struct odf_plan_s {
   int32_t compute_points = 0;       // points per odf_compute batch
   odf::SlotLayout compute_slot{};
 
+  odf::StageTimer timer;
   std::mutex compute_mu;
   std::unique_ptr<odf::RequestLoop> loop;
 };

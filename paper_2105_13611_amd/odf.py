@@ -50,7 +50,8 @@ class OdfOptions(C.Structure):
                 ("kappa_c_ref", C.c_double), ("lambda_c_ref_nm", C.c_double),
                 ("kappa_c_power", C.c_double), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_int64), ("stream", C.c_void_p),
-                ("max_batch_points", C.c_int32), ("loop_streams", C.c_int32)]
+                ("max_batch_points", C.c_int32), ("loop_streams", C.c_int32),
+                ("kernel_timing", C.c_int32)]
 
 
 class OdfRequest(C.Structure):
@@ -88,6 +89,7 @@ SIGNATURES = {
     "odf_stage_fine": (C.c_int, [C.c_void_p, C.POINTER(OdfRequest), C.c_int32, C.c_void_p]),
     "odf_stage_reduce": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "odf_debug_fail_next_batch": (C.c_int, [C.c_void_p, C.c_int64]),
+    "odf_stage_times": (C.c_int, [C.c_void_p, _D, _I64, C.c_int32]),
 }
 
 
@@ -179,7 +181,7 @@ class Plan:
     """
 
     def __init__(self, lines, species, layout, options, workspace_bytes=None, device="cuda:0",
-                 max_batch_points=0, loop_streams=0, stream=None):
+                 max_batch_points=0, loop_streams=0, stream=None, kernel_timing=False):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -214,7 +216,8 @@ class Plan:
                           options.window_cap_doppler, options.pe_over_p, options.kappa_c_ref,
                           options.lambda_c_ref_nm, options.kappa_c_power,
                           C.c_void_p(self.workspace.data_ptr()), int(workspace_bytes),
-                          C.c_void_p(self.stream.cuda_stream), int(max_batch_points), int(loop_streams))
+                          C.c_void_p(self.stream.cuda_stream), int(max_batch_points), int(loop_streams),
+                          int(bool(kernel_timing)))
         h = C.c_void_p()
         _check(lib().odf_plan(C.byref(cl), C.byref(cs), C.byref(self.layout_c), C.byref(opts), C.byref(h)))
         self.handle = h
@@ -287,6 +290,15 @@ class Plan:
         if d["state"] in ("DONE", "FAILED"):
             self._outs.pop(int(ticket), None)
         return d
+
+    STAGES = ("point_state", "select", "scan", "emit", "voigt", "odf")
+
+    def stage_times(self, reset=True):
+        """{stage: (total ms, launches)} from the HIP events of odf_compute."""
+        ms = np.zeros(6)
+        n = np.zeros(6, np.int64)
+        _check(lib().odf_stage_times(self.handle, _ptr(ms, _D), _ptr(n, _I64), int(bool(reset))))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.STAGES)}
 
     def fail_next_batch(self, ticket):
         _check(lib().odf_debug_fail_next_batch(self.handle, int(ticket)))

@@ -60,7 +60,7 @@ def _plan_args(w, **over):
     keep["_lk"] = lk
     o = w.options
     opts = odf.OdfOptions(0, 0, o.cutoff, o.window_cap_doppler, o.pe_over_p, o.kappa_c_ref,
-                          o.lambda_c_ref_nm, o.kappa_c_power, C.c_void_p(1), 1 << 20, None, 0, 0)
+                          o.lambda_c_ref_nm, o.kappa_c_power, C.c_void_p(1), 1 << 20, None, 0, 0, 0)
     return cl, cs, lay, opts, keep
 
 
