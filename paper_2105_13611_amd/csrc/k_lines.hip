@@ -265,30 +265,40 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
     const double Jd = rint(j0);
     const int32_t J = (int32_t)Jd;
     const int64_t slot = (int64_t)p * B.rec_stride + off;
+    const double c1 = P.lnq / e.b;
+    int32_t czh;
+    if (kRec64) {
+      czh = e.a < kFarR64 ? zone_half(kFarR64, c1) : -1;
+    } else {
+      const int32_t far = e.a < kFarR32 ? zone_half(kFarR32, c1) : -1;
+      const int32_t ring = e.a < kRingR32 ? zone_half(kRingR32, c1) : -1;
+      czh = (int32_t)(((uint32_t)ring << 16) | ((uint32_t)far & 0xffffu));
+    }
     if (kRec64) {
       Rec64 r;
       r.J = J;
       r.jlo = e.jlo;
       r.jhi = e.jhi;
+      r.czh = czh;
       r.li = (int32_t)i;
+      r.pad0 = r.pad1 = r.pad2 = 0;
       r.phi = j0 - Jd;
       r.S = e.S;
       r.y = e.a;
-      r.c1 = P.lnq / e.b;
+      r.c1 = c1;
       reinterpret_cast<Rec64*>(B.rec)[slot] = r;
     } else {
       Rec32 r;
       r.J = J;
       r.jlo = e.jlo;
       r.jhi = e.jhi;
-      r.li = (int32_t)i;
+      r.czh = czh;
       r.phi = (float)(j0 - Jd);
-      r.S = (float)e.S;
+      r.c1 = (float)c1;
+      r.C1 = (float)(e.S * e.a / kSqrtPi);
       r.y = (float)e.a;
-      r.c1 = (float)(P.lnq / e.b);
       reinterpret_cast<Rec32*>(B.rec)[slot] = r;
     }
-    B.win[slot] = make_int2(e.jlo, e.jhi);
     half = max(J - e.jlo, e.jhi - J) + 1;
     ns = (unsigned long long)(e.jhi - e.jlo + 1);
   }

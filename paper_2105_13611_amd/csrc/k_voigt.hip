@@ -5,20 +5,24 @@
 // Owner-computes tiling: a wave owns 1024 consecutive fine points (16 rows
 // of 64 lanes, one point per lane per row) and keeps their sums in
 // registers.  It walks the wavelength-sorted survivors whose centres lie
-// within the point's largest half-window of its points, tests 64 windows at
-// a time with one ballot, and for each intersecting line evaluates only the
-// rows the window covers.  No atomics: each point is summed by one lane in
-// the survivors' wavelength order, so results are bit-reproducible.
+// within the point's largest half-window of its points, one record per lane
+// (the next 64 prefetched while the current 64 are summed), tests their
+// windows with one ballot, broadcasts each intersecting record with readlane
+// and evaluates only the rows the window covers.  No atomics: each point is
+// summed by one lane in the survivors' wavelength order, so results are
+// bit-reproducible.
 //
 // Re w is evaluated in real arithmetic only, so that its relative accuracy
 // holds where Re w << |w| (far wings of weakly damped lines):
-//  - far from the core, a Gauss-Hermite quadrature of
+//  - away from the core, a Gauss-Hermite quadrature of
 //    H = (a/pi) int exp(-t^2) / ((x - t)^2 + a^2) dt, written as one fraction
 //    of positive terms (nodes and weights computed at plan time);
 //  - near the core, the trapezoidal rule for the same integral with the
 //    contribution of the integrand's pole at t = x + i a added in closed
 //    form (the error of the corrected rule is of order exp(-pi^2/h^2)); the
 //    node grid is shifted by half a step when x lies near a node.
+// Each row of 64 points takes one of these forms for all its lanes, chosen
+// from the smallest |x| in the row, so the wave never diverges.
 // Mixed precision uses FP32 with Kahan-compensated sums (every summand is
 // positive, so the compensated error bound is relative to the sum); the
 // plain path uses FP64 throughout.
@@ -30,6 +34,9 @@ namespace {
 
 constexpr float kInvSqrtPiF = 0.56418958354775628695f;
 constexpr float kPiF = 3.14159265358979323846f;
+constexpr float kSqrtPiF = 1.77245385090551602730f;
+// waves per SIMD the FP32 kernel is compiled for (VGPR budget 512 / waves)
+constexpr int kMinWaves32 = 1;
 
 __device__ __forceinline__ int xcd_remap(int bid, int total) {
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
@@ -68,22 +75,23 @@ __device__ __forceinline__ int upper_bound_J(const Rec* __restrict__ r, int n, i
 
 // ---------------------------------------------------------------- FP32 ----
 
-// General FP32 H(x, y) for any |z| (core rows).
-__device__ __forceinline__ float voigt32(float x, float y, const QuadConsts& Q) {
-  const float x2 = x * x, y2 = y * y, r2 = x2 + y2;
-  if (r2 >= kFarR32 * kFarR32) {
-    const float u = r2 + Q.gh2_t2;
-    return (y * kInvSqrtPiF) * u * __builtin_amdgcn_rcpf(fmaf(u, u, -4.0f * Q.gh2_t2 * x2));
-  }
-  if (r2 >= kRingR32 * kRingR32) {
-    const float p1 = r2 + Q.gh4_t2[0], p2 = r2 + Q.gh4_t2[1];
-    const float d1 = fmaf(p1, p1, -4.0f * Q.gh4_t2[0] * x2);
-    const float d2 = fmaf(p2, p2, -4.0f * Q.gh4_t2[1] * x2);
-    const float num = fmaf(Q.gh4_w[0] * p1, d2, Q.gh4_w[1] * p2 * d1);
-    return 2.0f * y * num * __builtin_amdgcn_rcpf(d1 * d2);
-  }
-  // pole-corrected trapezoid, nodes t_k = (k + delta) h
-  const float invh = 1.0f / kTrap32H;
+// Four-node Gauss-Hermite pair sum, valid to 2e-5 relative for |z| >= 6.
+__device__ __forceinline__ float ring32(float x, float y, const QuadConsts* __restrict__ Q) {
+  const float x2 = x * x, r2 = fmaf(y, y, x2);
+  const float p1 = r2 + Q->gh4_t2[0], p2 = r2 + Q->gh4_t2[1];
+  const float d1 = fmaf(p1, p1, -4.0f * Q->gh4_t2[0] * x2);
+  const float d2 = fmaf(p2, p2, -4.0f * Q->gh4_t2[1] * x2);
+  const float num = fmaf(Q->gh4_w[0] * p1, d2, Q->gh4_w[1] * p2 * d1);
+  return 2.0f * y * num * __builtin_amdgcn_rcpf(d1 * d2);
+}
+
+// Pole-corrected trapezoidal rule, nodes t_k = (k + delta) h, for y < 6 and
+// |x| up to about 30 (the running product is renormalised once so that it
+// stays inside the FP32 range).
+__device__ __forceinline__ float core32(float x, float y, const QuadConsts* __restrict__ Q) {
+  constexpr float h = kTrap32H;
+  constexpr float invh = 1.0f / kTrap32H;
+  const float y2 = y * y;
   const float hx = x * invh;
   const float fr = hx - rintf(hx);
   const bool sh = fabsf(fr) < 0.25f;
@@ -91,176 +99,285 @@ __device__ __forceinline__ float voigt32(float x, float y, const QuadConsts& Q) 
   float num = 0.0f, den = 1.0f;
 #pragma unroll
   for (int k = -kTrap32Half; k <= kTrap32Half; ++k) {
-    const float t = ((float)k + delta) * kTrap32H;
+    const float t = ((float)k + delta) * h;
     const float dd = x - t;
     const float D = fmaf(dd, dd, y2);
-    const float ck = sh ? Q.tr32_ch[k + kTrap32Half] : Q.tr32_ci[k + kTrap32Half];
+    const float ck = sh ? Q->tr32_ch[k + kTrap32Half] : Q->tr32_ci[k + kTrap32Half];
     num = fmaf(num, D, ck * den);
     den *= D;
+    if (k == 0) {
+      const float sc = den > 1.0e18f ? 1.0e-18f : 1.0f;
+      num *= sc;
+      den *= sc;
+    }
   }
-  float h = y * num / den;
+  float v = y * num * __builtin_amdgcn_rcpf(den);
   if (y < kPiF * invh) {
-    // Re[ 2 e^{-z^2} / (1 -/+ e^{-2 pi i z / h}) ] with E = e^{-2 pi y/h} e^{2 pi i x/h}
+    // Re[ 2 e^{-z^2} / (1 -/+ e^{-2 pi i z / h}) ] with E = e^{-2 pi y/h} e^{2 pi i x/h};
+    // the hardware sine and cosine take their argument in revolutions
     const float e2 = 2.0f * kPiF * y * invh;
-    const float mag = __expf(y2 - x2 - e2);
+    const float mag = __expf(y2 - x * x - e2);
     const float ep = __expf(-e2);
-    float sph, cph, sth, cth;
-    sincospif(2.0f * hx, &sph, &cph);
-    sincospif(2.0f * hx - 2.0f * x * y / kPiF, &sth, &cth);
+    const float ph = hx - rintf(hx);
+    const float th0 = hx - x * y * (1.0f / kPiF);
+    const float th = th0 - rintf(th0);
+    const float sph = __builtin_amdgcn_sinf(ph), cph = __builtin_amdgcn_cosf(ph);
+    const float sth = __builtin_amdgcn_sinf(th), cth = __builtin_amdgcn_cosf(th);
     const float sgn = sh ? 1.0f : -1.0f;
     const float dre = fmaf(ep, cph, sgn), dim = ep * sph;
-    h += 2.0f * mag * (cth * dre + sth * dim) / fmaf(dre, dre, dim * dim);
+    v += 2.0f * mag * fmaf(cth, dre, sth * dim) * __builtin_amdgcn_rcpf(fmaf(dre, dre, dim * dim));
   }
-  return h;
+  return v;
+}
+
+// Line parameters broadcast to the wave (uniform values).
+struct Line32 {
+  int J, jlo, jhi, czh;
+  float phi, c1, C1, y;
+};
+
+__device__ __forceinline__ Line32 read_line32(const Rec32& r, int k) {
+  Line32 l;
+  l.J = __builtin_amdgcn_readlane(r.J, k);
+  l.jlo = __builtin_amdgcn_readlane(r.jlo, k);
+  l.jhi = __builtin_amdgcn_readlane(r.jhi, k);
+  l.czh = __builtin_amdgcn_readlane(r.czh, k);
+  l.phi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.phi), k));
+  l.c1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.c1), k));
+  l.C1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.C1), k));
+  l.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.y), k));
+  return l;
+}
+
+// Per-line constants of the far-wing evaluation.  With u = x^2 + y^2 + 1/2,
+// the two-node pair sum is S H = C1 u / (u^2 - 2 x^2), written in x^2 as
+//   (C1 x^2 + C1 C2) / (x^2 (x^2 + K1) + K2),  C2 = y^2 + 1/2,
+//   K1 = 2 y^2 - 1, K2 = C2^2;
+// in the Lorentz limit (y >= 1e4) S H = C1 / (x^2 + y^2).
+struct Far32 {
+  float c1, c2, c3;   // x(d) = d (c1 + c2 d + c3 d^2)
+  float step;         // x(row + 1) = x(row) q^-64 + step
+  float A, B, K1, K2; // numerator A x^2 + B, denominator x^2 (x^2 + K1) + K2
+};
+
+// Bit mask of the rows (of the wave's 16) that meet [J - half, J + half].
+__device__ __forceinline__ unsigned zone_rows(int J, int half, int t_lo) {
+  if (half < 0) return 0u;
+  const int a = J - half - t_lo, b = J + half - t_lo;
+  if (b < 0 || a > kWavePoints - 1) return 0u;
+  const int lo = max(a, 0) >> 6, hi = min(b, kWavePoints - 1) >> 6;
+  return ((2u << hi) - 1u) & ~((1u << lo) - 1u);
 }
 
 template <bool kLorentz>
-__device__ __forceinline__ void far_rows32(const Rec32& r, int t_lo, int lane, int r_lo, int r_hi,
-                                           int rc_lo, int rc_hi, float c1, float c2, float c3,
-                                           float C1, float C2, float (&as)[kRows],
-                                           float (&ac)[kRows]) {
-  const int ib = r.J - t_lo - lane;
+__device__ __forceinline__ float far_value(float x, const Far32& f) {
+  const float x2 = x * x;
+  if (kLorentz) return f.A * __builtin_amdgcn_rcpf(x2 + f.K2);
+  return fmaf(x2, f.A, f.B) * __builtin_amdgcn_rcpf(fmaf(x2, x2 + f.K1, f.K2));
+}
+
+__device__ __forceinline__ float x_of_d32(float d, const Far32& f) {
+  return d * fmaf(d, fmaf(d, f.c3, f.c2), f.c1);
+}
+
+// The window covers all 1024 points and no row is near the core: sixteen
+// rows in one block, no branches, no masks.  x is taken from the index
+// every fourth row and carried to the next row by the exact frequency
+// ratio q^-64 in between (one FMA).
+template <bool kLorentz>
+__device__ __forceinline__ void full_rows32(float d0, float q64, const Far32& f,
+                                            float (&p)[kRows]) {
+#pragma unroll
+  for (int g = 0; g < kRows; g += 4) {
+    float x = x_of_d32(d0 - (float)(64 * g), f);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      p[g + r] += far_value<kLorentz>(x, f);
+      x = fmaf(x, q64, f.step);
+    }
+  }
+}
+
+// Far rows wholly inside the window (bit mask), x from the index.
+template <bool kLorentz>
+__device__ __forceinline__ void inner_rows32(unsigned rows, float d0, const Far32& f,
+                                             float (&p)[kRows]) {
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) {
-    if (rr < r_lo || rr > r_hi) continue;
-    if (rr >= rc_lo && rr <= rc_hi) continue;
-    const float d = (float)(ib - 64 * rr) + r.phi;
-    const float x = d * fmaf(d, fmaf(d, c3, c2), c1);
-    const float x2 = x * x;
-    float v;
-    if (kLorentz) {
-      v = C1 * __builtin_amdgcn_rcpf(x2 + C2);
-    } else {
-      const float u = x2 + C2;
-      v = (u * C1) * __builtin_amdgcn_rcpf(fmaf(u, u, -2.0f * x2));
-    }
-    const int rs = t_lo + 64 * rr;
-    if (!(rs >= r.jlo && rs + 63 <= r.jhi)) {
-      const int j = rs + lane;
-      v = (j >= r.jlo && j <= r.jhi) ? v : 0.0f;
-    }
-    kahan_add(as[rr], ac[rr], v);
+    if (!((rows >> rr) & 1u)) continue;
+    p[rr] += far_value<kLorentz>(x_of_d32(d0 - (float)(64 * rr), f), f);
   }
 }
 
-__device__ __forceinline__ void line32(const Rec32& r, int t_lo, int t_hi, int lane, float lnq,
-                                       const QuadConsts& Q, float (&as)[kRows], float (&ac)[kRows],
-                                       float* __restrict__ ls, float* __restrict__ lc) {
-  const int jl = max(r.jlo, t_lo) - t_lo;
-  const int jh = min(r.jhi, t_hi) - t_lo;
-  const int r_lo = jl >> 6, r_hi = jh >> 6;
-  // x = expm1(d ln q) / b = d (c1 + c2 d + c3 d^2) + O(d^4 ln q^3), |d ln q| <= 0.031
-  const float c1 = r.c1;
-  const float c2 = c1 * lnq * 0.5f;
-  const float c3 = c1 * lnq * lnq * (1.0f / 6.0f);
-  const float y = r.y;
-  // rows that may contain |z| < 15 need the general evaluation
-  int rc_lo = 1, rc_hi = 0;
-  if (y < kFarR32) {
-    const float Dc = kFarR32 * 1.02f / c1 + 2.0f;
-    const float ctr = (float)(r.J - t_lo) + r.phi;
-    rc_lo = ((int)floorf(ctr - Dc)) >> 6;
-    rc_hi = ((int)ceilf(ctr + Dc)) >> 6;
-  }
-  if (y >= 1.0e4f) {
-    // Lorentz limit: the Gauss-Hermite pair correction is below 1/(2 y^2)
-    far_rows32<true>(r, t_lo, lane, r_lo, r_hi, rc_lo, rc_hi, c1, c2, c3,
-                     r.S * y * kInvSqrtPiF, y * y, as, ac);
+__device__ __forceinline__ void line32(const Line32& l, int t_lo, int t_hi, int lane, float lnq2,
+                                       float lnq6, float q64, float g64,
+                                       const QuadConsts* __restrict__ Q, float (&p)[kRows],
+                                       float* __restrict__ lp) {
+  Far32 f;
+  f.c1 = l.c1;
+  f.c2 = l.c1 * lnq2;
+  f.c3 = l.c1 * lnq6;
+  f.step = g64 * l.c1;
+  const bool lor = l.y >= 1.0e4f;   // Lorentz limit: pair correction below 1/(2 y^2)
+  const float y2 = l.y * l.y;
+  if (lor) {
+    f.A = l.C1;
+    f.B = 0.0f;
+    f.K1 = 0.0f;
+    f.K2 = y2;
   } else {
-    far_rows32<false>(r, t_lo, lane, r_lo, r_hi, rc_lo, rc_hi, c1, c2, c3,
-                      r.S * y * kInvSqrtPiF, fmaf(y, y, Q.gh2_t2), as, ac);
+    const float C2 = y2 + Q->gh2_t2;
+    f.A = l.C1;
+    f.B = l.C1 * C2;
+    f.K1 = fmaf(2.0f, y2, -1.0f);
+    f.K2 = C2 * C2;
   }
-  const int g_lo = max(r_lo, rc_lo), g_hi = min(r_hi, rc_hi);
-  const int ib = r.J - t_lo - lane;
-  for (int rr = g_lo; rr <= g_hi; ++rr) {
-    const float d = (float)(ib - 64 * rr) + r.phi;
-    const float x = d * fmaf(d, fmaf(d, c3, c2), c1);
-    float v = r.S * voigt32(x, y, Q);
+  const int ib = l.J - t_lo - lane;
+  const float d0 = (float)ib + l.phi;
+  const int zfar = (int)(short)(l.czh & 0xffff);   // |x| < 15 zone half-width
+  const int zring = l.czh >> 16;                   // |x| < 6 zone half-width
+  const unsigned near = zone_rows(l.J, zfar, t_lo);
+  if (!near && l.jlo <= t_lo && l.jhi >= t_lo + (kWavePoints - 1) &&
+      t_hi == t_lo + (kWavePoints - 1)) {
+    if (lor) full_rows32<true>(d0, q64, f, p);
+    else full_rows32<false>(d0, q64, f, p);
+    return;
+  }
+  const int jl = max(l.jlo, t_lo) - t_lo;
+  const int jh = min(l.jhi, t_hi) - t_lo;
+  const int r_lo = jl >> 6, r_hi = jh >> 6;
+  const unsigned rows = ((2u << r_hi) - 1u) & ~((1u << r_lo) - 1u);
+  // rows cut by the window edge (at most two)
+  unsigned edge = 0u;
+  if (l.jlo > t_lo + 64 * r_lo) edge |= 1u << r_lo;
+  if (l.jhi < t_lo + 64 * r_hi + 63) edge |= 1u << r_hi;
+  const unsigned nearr = near & rows;
+  const unsigned inner = rows & ~nearr & ~edge;
+  if (lor) inner_rows32<true>(inner, d0, f, p);
+  else inner_rows32<false>(inner, d0, f, p);
+  unsigned m = (nearr | edge) & rows;
+  if (!m) return;
+  // edge rows and rows near the core: per-lane masks, partial sums in LDS
+  const unsigned core = zone_rows(l.J, zring, t_lo);
+  const float S = l.C1 * (kSqrtPiF / l.y);
+  while (m) {
+    const int rr = __builtin_ctz(m);
+    m &= m - 1u;
+    const float d = (float)(ib - 64 * rr) + l.phi;   // exact near the centre
+    const float x = x_of_d32(d, f);
+    float v;
+    if ((nearr >> rr) & 1u) v = S * ((core >> rr) & 1u ? core32(x, l.y, Q) : ring32(x, l.y, Q));
+    else v = lor ? far_value<true>(x, f) : far_value<false>(x, f);
     const int j = t_lo + 64 * rr + lane;
-    v = (j >= r.jlo && j <= r.jhi) ? v : 0.0f;
-    const int o = rr * 64 + lane;
-    float s = ls[o], c = lc[o];
-    kahan_add(s, c, v);
-    ls[o] = s;
-    lc[o] = c;
+    v = (j >= l.jlo && j <= l.jhi) ? v : 0.0f;
+    lp[rr * 64 + lane] += v;
   }
 }
 
-__global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B, QuadConsts Q,
+// Compensated (Kahan) addition of the partial sums into the row sums: the
+// running sums s stay in registers, their compensations c in LDS.
+__device__ __forceinline__ void flush32(float (&s)[kRows], float (&p)[kRows],
+                                        float* __restrict__ lp, float* __restrict__ lc, int lane) {
+#pragma unroll
+  for (int rr = 0; rr < kRows; ++rr) {
+    const int o = rr * 64 + lane;
+    float c = lc[o];
+    kahan_add(s[rr], c, p[rr] + lp[o]);
+    lc[o] = c;
+    lp[o] = 0.0f;
+    p[rr] = 0.0f;
+  }
+}
+
+// lines summed in plain FP32 between two compensated additions
+constexpr int kFlushLines = 16;
+
+__global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
+                                                 const QuadConsts* __restrict__ Q,
                                                  int tiles_per_point, int total) {
-  __shared__ float lds_s[kWavesPerWG][kWavePoints];
-  __shared__ float lds_c[kWavesPerWG][kWavePoints];
+  __shared__ float lds_p[kWavesPerWG][kWavePoints];   // partial sums of core/ring rows
+  __shared__ float lds_c[kWavesPerWG][kWavePoints];   // Kahan compensations
   const int logical = xcd_remap(blockIdx.x, total);
   if (logical >= total) return;
-  const int p = logical / tiles_per_point;
-  const int tile = logical - p * tiles_per_point;
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int pt = logical / tiles_per_point;
+  const int tile = logical - pt * tiles_per_point;
+  // wave index is uniform across the wave; say so, so that everything derived
+  // from the tile origin stays in scalar registers and branches stay scalar
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int N = (int)P.N;
   const int t_lo = tile * kWGPoints + wid * kWavePoints;
   if (t_lo >= N) return;
   const int t_hi = min(t_lo + kWavePoints - 1, N - 1);
-  float* ls = lds_s[wid];
+  float* lp = lds_p[wid];
   float* lc = lds_c[wid];
+  float s[kRows], p[kRows];
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) {
-    ls[rr * 64 + lane] = 0.0f;
+    lp[rr * 64 + lane] = 0.0f;
     lc[rr * 64 + lane] = 0.0f;
+    s[rr] = 0.0f;
+    p[rr] = 0.0f;
   }
-  float as[kRows], ac[kRows];
-#pragma unroll
-  for (int rr = 0; rr < kRows; ++rr) {
-    as[rr] = 0.0f;
-    ac[rr] = 0.0f;
-  }
-  const Rec32* __restrict__ rec = reinterpret_cast<const Rec32*>(B.rec) + p * B.rec_stride;
-  const int2* __restrict__ win = B.win + p * B.rec_stride;
-  const int ns = B.nsurv[p];
-  const int H = B.hmax[p];
+  const Rec32* __restrict__ rec = reinterpret_cast<const Rec32*>(B.rec) + pt * B.rec_stride;
+  const int ns = B.nsurv[pt];
+  const int H = B.hmax[pt];
   const float lnq = (float)P.lnq;
+  const float lnq2 = lnq * 0.5f, lnq6 = lnq * lnq * (1.0f / 6.0f);
+  const float q64 = (float)exp(-64.0 * P.lnq);              // nu(j + 64) / nu(j)
+  const float g64 = (float)(expm1(-64.0 * P.lnq) / P.lnq);  // (q^-64 - 1) / ln q
   const int c0 = lower_bound_J(rec, ns, t_lo - H);
   const int c1 = upper_bound_J(rec, ns, t_hi + H);
+  int since_flush = 0;
+  // one record per lane, the next batch prefetched while this one is summed
+  Rec32 nxt{};
+  if (c0 + lane < c1) nxt = rec[c0 + lane];
   for (int base = c0; base < c1; base += 64) {
-    const int i = base + lane;
-    int2 w = make_int2(1, 0);
-    if (i < c1) w = win[i];
-    unsigned long long m = __ballot(w.x <= t_hi && w.y >= t_lo);
+    const Rec32 cur = nxt;
+    const bool valid = base + lane < c1;
+    if (base + 64 + lane < c1) nxt = rec[base + 64 + lane];
+    unsigned long long m = __ballot(valid && cur.jlo <= t_hi && cur.jhi >= t_lo);
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);
       m &= m - 1;
-      const Rec32 r = rec[base + k];
-      line32(r, t_lo, t_hi, lane, lnq, Q, as, ac, ls, lc);
+      line32(read_line32(cur, k), t_lo, t_hi, lane, lnq2, lnq6, q64, g64, Q, p, lp);
+      if (++since_flush == kFlushLines) {
+        flush32(s, p, lp, lc, lane);
+        since_flush = 0;
+      }
     }
   }
-  float* kap = reinterpret_cast<float*>(B.kappa) + p * B.kappa_stride;
+  flush32(s, p, lp, lc, lane);
+  float* kap = reinterpret_cast<float*>(B.kappa) + pt * B.kappa_stride;
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) {
     const int j = t_lo + rr * 64 + lane;
-    const int o = rr * 64 + lane;
-    if (j <= t_hi) kap[j] = (as[rr] - ac[rr]) + (ls[o] - lc[o]);
+    if (j <= t_hi) kap[j] = s[rr] - lc[rr * 64 + lane];
   }
 }
 
 // ---------------------------------------------------------------- FP64 ----
 
 // Eight-node Gauss-Hermite pair sum for |z| >= 10, one division.
-__device__ __forceinline__ double gh8(double x2, double y, double r2, const QuadConsts& Q) {
-  const double p1 = r2 + Q.gh8_t2[0];
-  const double d1 = fma(p1, p1, -4.0 * Q.gh8_t2[0] * x2);
-  double num = Q.gh8_w[0] * p1, den = d1;
+__device__ __forceinline__ double gh8(double x2, double y, double r2, const QuadConsts* __restrict__ Q) {
+  const double p1 = r2 + Q->gh8_t2[0];
+  const double d1 = fma(p1, p1, -4.0 * Q->gh8_t2[0] * x2);
+  double num = Q->gh8_w[0] * p1, den = d1;
 #pragma unroll
   for (int k = 1; k < 4; ++k) {
-    const double pk = r2 + Q.gh8_t2[k];
-    const double dk = fma(pk, pk, -4.0 * Q.gh8_t2[k] * x2);
-    num = fma(num, dk, Q.gh8_w[k] * pk * den);
+    const double pk = r2 + Q->gh8_t2[k];
+    const double dk = fma(pk, pk, -4.0 * Q->gh8_t2[k] * x2);
+    num = fma(num, dk, Q->gh8_w[k] * pk * den);
     den *= dk;
   }
   return 2.0 * y * num / den;
 }
 
-__device__ __forceinline__ double voigt64(double x, double y, const QuadConsts& Q) {
-  const double x2 = x * x, y2 = y * y, r2 = x2 + y2;
-  if (r2 >= kFarR64 * kFarR64) return gh8(x2, y, r2, Q);
-  const double invh = 1.0 / kTrap64H;
+// Pole-corrected trapezoidal rule (FP64), any x reached by a core row.
+__device__ __forceinline__ double core64(double x, double y, const QuadConsts* __restrict__ Q) {
+  constexpr double h = kTrap64H;
+  constexpr double invh = 1.0 / kTrap64H;
+  const double y2 = y * y;
   const double hx = x * invh;
   const double fr = hx - rint(hx);
   const bool sh = fabs(fr) < 0.25;
@@ -268,26 +385,26 @@ __device__ __forceinline__ double voigt64(double x, double y, const QuadConsts& 
   double num = 0.0, den = 1.0;
 #pragma unroll
   for (int k = -kTrap64Half; k <= kTrap64Half; ++k) {
-    const double t = ((double)k + delta) * kTrap64H;
+    const double t = ((double)k + delta) * h;
     const double dd = x - t;
     const double D = fma(dd, dd, y2);
-    const double ck = sh ? Q.tr64_ch[k + kTrap64Half] : Q.tr64_ci[k + kTrap64Half];
+    const double ck = sh ? Q->tr64_ch[k + kTrap64Half] : Q->tr64_ci[k + kTrap64Half];
     num = fma(num, D, ck * den);
     den *= D;
   }
-  double h = y * num / den;
+  double v = y * num / den;
   if (y < kPi * invh) {
     const double e2 = 2.0 * kPi * y * invh;
-    const double mag = exp(y2 - x2 - e2);
+    const double mag = exp(y2 - x * x - e2);
     const double ep = exp(-e2);
     double sph, cph, sth, cth;
     sincospi(2.0 * hx, &sph, &cph);
     sincospi(2.0 * hx - 2.0 * x * y / kPi, &sth, &cth);
     const double sgn = sh ? 1.0 : -1.0;
     const double dre = fma(ep, cph, sgn), dim = ep * sph;
-    h += 2.0 * mag * (cth * dre + sth * dim) / fma(dre, dre, dim * dim);
+    v += 2.0 * mag * (cth * dre + sth * dim) / fma(dre, dre, dim * dim);
   }
-  return h;
+  return v;
 }
 
 // x = expm1(u)/b = d c1 E(u), u = d ln q, E(u) = expm1(u)/u (Taylor to u^7,
@@ -305,56 +422,84 @@ __device__ __forceinline__ double x_of_d64(double d, double c1, double lnq) {
   return d * c1 * e;
 }
 
-__device__ __forceinline__ void line64(const Rec64& r, int t_lo, int t_hi, int lane, double lnq,
-                                       const QuadConsts& Q, double (&as)[kRows],
-                                       double* __restrict__ ls) {
-  const int jl = max(r.jlo, t_lo) - t_lo;
-  const int jh = min(r.jhi, t_hi) - t_lo;
+struct Line64 {
+  int J, jlo, jhi, czh;
+  double phi, S, y, c1;
+};
+
+__device__ __forceinline__ double readlane_f64(double v, int k) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ Line64 read_line64(const Rec64& r, int k) {
+  Line64 l;
+  l.J = __builtin_amdgcn_readlane(r.J, k);
+  l.jlo = __builtin_amdgcn_readlane(r.jlo, k);
+  l.jhi = __builtin_amdgcn_readlane(r.jhi, k);
+  l.czh = __builtin_amdgcn_readlane(r.czh, k);
+  l.phi = readlane_f64(r.phi, k);
+  l.S = readlane_f64(r.S, k);
+  l.y = readlane_f64(r.y, k);
+  l.c1 = readlane_f64(r.c1, k);
+  return l;
+}
+
+__device__ __forceinline__ void line64(const Line64& l, int t_lo, int t_hi, int lane, double lnq,
+                                       double q64, double g64, const QuadConsts* __restrict__ Q,
+                                       double (&as)[kRows], double* __restrict__ ls) {
+  const double y2 = l.y * l.y;
+  const int ib = l.J - t_lo - lane;
+  const int jl = max(l.jlo, t_lo) - t_lo;
+  const int jh = min(l.jhi, t_hi) - t_lo;
   const int r_lo = jl >> 6, r_hi = jh >> 6;
-  const double c1 = r.c1, y = r.y, S = r.S;
-  int rc_lo = 1, rc_hi = 0;
-  if (y < kFarR64) {
-    const double Dc = kFarR64 * 1.02 / c1 + 2.0;
-    const double ctr = (double)(r.J - t_lo) + r.phi;
-    rc_lo = ((int)floor(ctr - Dc)) >> 6;
-    rc_hi = ((int)ceil(ctr + Dc)) >> 6;
-  }
-  const double y2 = y * y;
-  const int ib = r.J - t_lo - lane;
+  const unsigned rows = ((2u << r_hi) - 1u) & ~((1u << r_lo) - 1u);
+  const unsigned core = zone_rows(l.J, l.czh, t_lo) & rows;
+  const unsigned far = rows & ~core;
+  // x from the index at the first row of each run of rows, then carried to
+  // the next row by the exact frequency ratio q^-64 (one FMA)
+  const double step = g64 * l.c1;
+  double x = 0.0;
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) {
-    if (rr < r_lo || rr > r_hi) continue;
-    if (rr >= rc_lo && rr <= rc_hi) continue;
-    const double d = (double)(ib - 64 * rr) + r.phi;
-    const double x = x_of_d64(d, c1, lnq);
+    if (!(far & (1u << rr))) continue;
+    if (rr == 0 || !((far >> (rr - 1)) & 1u)) x = x_of_d64((double)(ib - 64 * rr) + l.phi, l.c1, lnq);
+    else x = fma(x, q64, step);
     const double x2 = x * x;
-    double v = S * gh8(x2, y, x2 + y2, Q);
+    double v = l.S * gh8(x2, l.y, x2 + y2, Q);
     const int rs = t_lo + 64 * rr;
-    if (!(rs >= r.jlo && rs + 63 <= r.jhi)) {
+    if (rs < l.jlo || rs + 63 > l.jhi) {
       const int j = rs + lane;
-      v = (j >= r.jlo && j <= r.jhi) ? v : 0.0;
+      v = (j >= l.jlo && j <= l.jhi) ? v : 0.0;
     }
     as[rr] += v;
   }
-  const int g_lo = max(r_lo, rc_lo), g_hi = min(r_hi, rc_hi);
-  for (int rr = g_lo; rr <= g_hi; ++rr) {
-    const double d = (double)(ib - 64 * rr) + r.phi;
-    const double x = x_of_d64(d, c1, lnq);
-    double v = S * voigt64(x, y, Q);
+  unsigned m = core;
+  while (m) {
+    const int rr = __builtin_ctz(m);
+    m &= m - 1u;
+    const double d = (double)(ib - 64 * rr) + l.phi;
+    const double x = x_of_d64(d, l.c1, lnq);
+    double v = l.S * core64(x, l.y, Q);
     const int j = t_lo + 64 * rr + lane;
-    v = (j >= r.jlo && j <= r.jhi) ? v : 0.0;
+    v = (j >= l.jlo && j <= l.jhi) ? v : 0.0;
     ls[rr * 64 + lane] += v;
   }
 }
 
-__global__ __launch_bounds__(256) void k_voigt64(Params P, Batch B, QuadConsts Q,
+__global__ __launch_bounds__(256) void k_voigt64(Params P, Batch B, const QuadConsts* __restrict__ Q,
                                                  int tiles_per_point, int total) {
   __shared__ double lds_s[kWavesPerWG][kWavePoints];
   const int logical = xcd_remap(blockIdx.x, total);
   if (logical >= total) return;
   const int p = logical / tiles_per_point;
   const int tile = logical - p * tiles_per_point;
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // wave index is uniform across the wave; say so, so that everything derived
+  // from the tile origin stays in scalar registers and branches stay scalar
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int N = (int)P.N;
   const int t_lo = tile * kWGPoints + wid * kWavePoints;
   if (t_lo >= N) return;
@@ -366,22 +511,24 @@ __global__ __launch_bounds__(256) void k_voigt64(Params P, Batch B, QuadConsts Q
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) as[rr] = 0.0;
   const Rec64* __restrict__ rec = reinterpret_cast<const Rec64*>(B.rec) + p * B.rec_stride;
-  const int2* __restrict__ win = B.win + p * B.rec_stride;
   const int ns = B.nsurv[p];
   const int H = B.hmax[p];
   const double lnq = P.lnq;
+  const double q64 = exp(-64.0 * lnq);              // nu(j + 64) / nu(j)
+  const double g64 = expm1(-64.0 * lnq) / lnq;      // (q^-64 - 1) / ln q
   const int c0 = lower_bound_J(rec, ns, t_lo - H);
   const int c1 = upper_bound_J(rec, ns, t_hi + H);
+  Rec64 nxt{};
+  if (c0 + lane < c1) nxt = rec[c0 + lane];
   for (int base = c0; base < c1; base += 64) {
-    const int i = base + lane;
-    int2 w = make_int2(1, 0);
-    if (i < c1) w = win[i];
-    unsigned long long m = __ballot(w.x <= t_hi && w.y >= t_lo);
+    const Rec64 cur = nxt;
+    const bool valid = base + lane < c1;
+    if (base + 64 + lane < c1) nxt = rec[base + 64 + lane];
+    unsigned long long m = __ballot(valid && cur.jlo <= t_hi && cur.jhi >= t_lo);
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);
       m &= m - 1;
-      const Rec64 r = rec[base + k];
-      line64(r, t_lo, t_hi, lane, lnq, Q, as, ls);
+      line64(read_line64(cur, k), t_lo, t_hi, lane, lnq, q64, g64, Q, as, ls);
     }
   }
   double* kap = reinterpret_cast<double*>(B.kappa) + p * B.kappa_stride;
@@ -394,7 +541,7 @@ __global__ __launch_bounds__(256) void k_voigt64(Params P, Batch B, QuadConsts Q
 
 }  // namespace
 
-hipError_t launch_voigt(hipStream_t st, const Params& P, const Batch& B, const QuadConsts& Q) {
+hipError_t launch_voigt(hipStream_t st, const Params& P, const Batch& B, const QuadConsts* __restrict__ Q) {
   if (B.n_points == 0) return hipSuccess;
   const int tiles = (int)((P.N + kWGPoints - 1) / kWGPoints);
   const int total = tiles * B.n_points;

@@ -28,18 +28,27 @@ constexpr int kWGPoints = kWavePoints * kWavesPerWG;  // 4096 per workgroup
 constexpr int kLineBlock = 256;                  // lines per workgroup in K1
 
 // ---- Voigt region constants -----------------------------------------------
-// FP32: |z| >= 15 two-node Gauss-Hermite pair, 6 <= |z| < 15 four-node,
-// |z| < 6 pole-corrected trapezoidal rule (h = 0.7, nodes |t| <= 4.5).
+// FP32: rows of 64 fine points are classified by the smallest |x| in them:
+// all |x| >= 15 -> two-node Gauss-Hermite pair; all |x| >= 6 -> four-node;
+// otherwise the pole-corrected trapezoidal rule (h = 0.75, nodes |t| <= 4.2)
+// for every lane of the row.
 constexpr float kFarR32 = 15.0f;
 constexpr float kRingR32 = 6.0f;
-constexpr int kTrap32Half = 7;                   // k = -7..7
-constexpr float kTrap32H = 0.7f;
-constexpr float kTrap32Tmax = 4.5f;
-// FP64: |z| >= 10 eight-node Gauss-Hermite pair sum, else trapezoid h=0.5, |t|<=6
+constexpr int kTrap32Half = 6;                   // k = -6..6
+constexpr float kTrap32H = 0.75f;
+constexpr float kTrap32Tmax = 4.2f;
+// FP64: rows with all |x| >= 10 -> eight-node Gauss-Hermite pair sum; other
+// rows -> trapezoid h = 0.5, nodes |t| <= 6, for every lane.
 constexpr double kFarR64 = 10.0;
 constexpr int kTrap64Half = 12;                  // k = -12..12
 constexpr double kTrap64H = 0.5;
 constexpr double kTrap64Tmax = 6.0;
+
+// Half-width in fine points of the zone where |x| < R may occur, for a line
+// with c1 = ln q / b: |x| >= R implies |d| >= R / (1.02 c1) (|d ln q| <= 0.031).
+__host__ __device__ inline int32_t zone_half(double R, double c1) {
+  return (int32_t)ceil(R * 1.02 / c1) + 2;
+}
 
 // Quadrature constants computed on the host at plan time.
 struct QuadConsts {
@@ -78,19 +87,23 @@ struct PointState {
   double pad;
 };
 
-// Survivor records.  `win` (j_lo, j_hi) is kept apart for the wave-wide
-// intersection test; the record is read once per intersecting line.
+// Survivor records, one per kept line and point, in wavelength order.  A
+// wave loads 64 of them at a time (one per lane), tests their windows
+// against its tile with one ballot and broadcasts each intersecting record
+// with readlane.  `czh` is the half-width in fine points of the zone around
+// the centre where |x + i a| may be below the far-wing radius (-1: none).
 struct alignas(16) Rec32 {
   int32_t J;        // nearest integer of the fractional centre index
   int32_t jlo, jhi; // window, clipped to the grid
-  int32_t li;       // sorted line index
+  int32_t czh;      // zone half-widths: low 16 bits |x| < 15, high 16 bits |x| < 6 (-1: none)
   float phi;        // fractional centre minus J, in [-1/2, 1/2]
-  float S;          // line strength [cm^2/g]
+  float c1;         // ln q / b, so x ~= d c1 (1 + d ln q / 2 + ...)
+  float C1;         // S a / sqrt(pi)
   float y;          // damping parameter a
-  float c1;         // ln q / b
 };
 struct alignas(16) Rec64 {
-  int32_t J, jlo, jhi, li;
+  int32_t J, jlo, jhi, czh;
+  int32_t li, pad0, pad1, pad2;   // sorted line index (stage checks)
   double phi, S, y, c1;
 };
 
@@ -110,7 +123,6 @@ struct Batch {
   int32_t* hmax;        // [B]         max half-window in fine points
   unsigned long long* nsamp;  // [B]
   void* rec;            // [B][L] Rec32 or Rec64
-  int2* win;            // [B][L]
   void* kappa;          // [B][N] float or double
   int64_t rec_stride;   // = L
   int64_t kappa_stride; // = N
@@ -146,7 +158,7 @@ hipError_t launch_point_state(hipStream_t st, const Params& P, const Batch& B);
 hipError_t launch_select(hipStream_t st, const Params& P, const DevLines& L, const Batch& B);
 hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const Batch& B);
 hipError_t launch_emit(hipStream_t st, const Params& P, const DevLines& L, const Batch& B, int rec64);
-hipError_t launch_voigt(hipStream_t st, const Params& P, const Batch& B, const QuadConsts& Q);
+hipError_t launch_voigt(hipStream_t st, const Params& P, const Batch& B, const QuadConsts* Q);
 hipError_t launch_odf(hipStream_t st, const Params& P, const void* kappa, int64_t kappa_stride,
                       int32_t n_points, void* out, int max_bin, void* gscratch,
                       const int64_t* goff, int64_t gscratch_stride);

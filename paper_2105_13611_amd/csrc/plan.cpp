@@ -197,7 +197,6 @@ SlotLayout make_slot(const odf_plan_s* p, int32_t pts) {
   s.off_hmax = take(4 * pts);
   s.off_nsamp = take(8 * pts);
   s.off_rec = take((mixed ? (int64_t)sizeof(Rec32) : (int64_t)sizeof(Rec64)) * std::max<int64_t>(L, 1) * pts);
-  s.off_win = take(8 * std::max<int64_t>(L, 1) * pts);
   s.off_kappa = take((mixed ? 4 : 8) * p->N * pts);
   s.off_gscr = take((mixed ? 4 : 8) * std::max<int64_t>(p->gscr_elems, 1) * pts);
   s.bytes = o;
@@ -221,7 +220,6 @@ Batch make_batch(const odf_plan_s* p, const SlotLayout& s, char* base, int32_t n
   B.hmax = reinterpret_cast<int32_t*>(base + s.off_hmax);
   B.nsamp = reinterpret_cast<unsigned long long*>(base + s.off_nsamp);
   B.rec = base + s.off_rec;
-  B.win = reinterpret_cast<int2*>(base + s.off_win);
   B.kappa = base + s.off_kappa;
   B.rec_stride = std::max<int64_t>(p->n_lines, 1);
   B.kappa_stride = p->N;
@@ -263,7 +261,7 @@ odf_status enqueue_batch(odf_plan_s* p, const Batch& B, char* slot_base, const S
   { TimedLaunch tl(timer, st, 1); HIP_TRY(launch_select(st, p->params, p->lines, B)); }
   { TimedLaunch tl(timer, st, 2); HIP_TRY(launch_scan(st, p->params, p->lines, B)); }
   { TimedLaunch tl(timer, st, 3); HIP_TRY(launch_emit(st, p->params, p->lines, B, p->opts.precision == ODF_PREC_FP64)); }
-  { TimedLaunch tl(timer, st, 4); HIP_TRY(launch_voigt(st, p->params, B, p->quad)); }
+  { TimedLaunch tl(timer, st, 4); HIP_TRY(launch_voigt(st, p->params, B, p->d_quad)); }
   if (out) {
     TimedLaunch tl(timer, st, 5);
     HIP_TRY(launch_odf(st, p->params, B.kappa, B.kappa_stride, B.n_points, out, p->max_bin,
@@ -482,6 +480,16 @@ odf_status odf_plan(const odf_lines* lines, const odf_species* species, const od
     P.precision = p->opts.precision == ODF_PREC_MIXED ? 1 : 0;
   }
   p->quad = make_quad_consts();
+  {
+    odf_plan_s* pp = p.get();
+    if ((st = dev_alloc(pp, &pp->d_quad, 1)) != ODF_OK) { free_owned(pp); return st; }
+    hipError_t e = hipMemcpy(pp->d_quad, &pp->quad, sizeof(QuadConsts), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      set_error("quadrature upload failed: %s", hipGetErrorString(e));
+      free_owned(pp);
+      return ODF_E_DEVICE;
+    }
+  }
 
   // workspace: points per odf_compute batch
   const SlotLayout one = make_slot(p.get(), 1);
@@ -580,7 +588,7 @@ odf_status odf_compute(odf_plan_t* p, const odf_request* r, odf_stats* stats) {
 // ---- stage entry points ------------------------------------------------------
 
 static odf_status stage_prefix(odf_plan_t* p, const odf_request* r, int32_t point, Batch* B,
-                               int rec64, void* rec_override, int2* win_override) {
+                               int rec64, void* rec_override) {
   hipStream_t s = static_cast<hipStream_t>(p->opts.stream);
   char* base = static_cast<char*>(p->opts.workspace);
   const SlotLayout& sl = p->compute_slot;
@@ -590,7 +598,6 @@ static odf_status stage_prefix(odf_plan_t* p, const odf_request* r, int32_t poin
   HIP_TRY(hipMemcpyAsync(base + sl.off_vt, r->vturb_kms + point, 8, hipMemcpyHostToDevice, s));
   *B = make_batch(p, sl, base, 1);
   if (rec_override) B->rec = rec_override;
-  if (win_override) B->win = win_override;
   HIP_TRY(launch_point_state(s, p->params, *B));
   HIP_TRY(launch_select(s, p->params, p->lines, *B));
   HIP_TRY(launch_scan(s, p->params, p->lines, *B));
@@ -616,7 +623,7 @@ odf_status odf_stage_lines(odf_plan_t* p, const odf_request* r, int32_t point, i
   Rec64* rec = nullptr;
   if (hipMalloc(&rec, L * sizeof(Rec64)) != hipSuccess) { set_error("hipMalloc failed"); return ODF_E_DEVICE; }
   Batch B;
-  st = stage_prefix(p, r, point, &B, 1, rec, nullptr);
+  st = stage_prefix(p, r, point, &B, 1, rec);
   hipStream_t s = static_cast<hipStream_t>(p->opts.stream);
   int32_t ns = 0;
   unsigned long long nsamp = 0;
@@ -660,9 +667,9 @@ odf_status odf_stage_fine(odf_plan_t* p, const odf_request* r, int32_t point, vo
   WorkspaceLease lease(p->loop.get());
   Batch B;
   const int rec64 = p->opts.precision == ODF_PREC_FP64;
-  if ((st = stage_prefix(p, r, point, &B, rec64, nullptr, nullptr)) != ODF_OK) return st;
+  if ((st = stage_prefix(p, r, point, &B, rec64, nullptr)) != ODF_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(p->opts.stream);
-  HIP_TRY(launch_voigt(s, p->params, B, p->quad));
+  HIP_TRY(launch_voigt(s, p->params, B, p->d_quad));
   const size_t esz = p->opts.precision == ODF_PREC_MIXED ? 4 : 8;
   HIP_TRY(hipMemcpyAsync(kappa_dev, B.kappa, p->N * esz, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));

@@ -25,7 +25,7 @@ void g_last_error_clear();
 // Layout of one batch slot inside the workspace.
 struct SlotLayout {
   int64_t off_T, off_logP, off_vt, off_abund, off_state, off_pop, off_bT, off_flags, off_blk,
-      off_nsurv, off_hmax, off_nsamp, off_rec, off_win, off_kappa, off_gscr;
+      off_nsurv, off_hmax, off_nsamp, off_rec, off_kappa, off_gscr;
   int64_t bytes;      // total bytes of the slot
   int32_t points;     // points per slot
 };
@@ -62,6 +62,7 @@ struct odf_plan_s {
   odf::DevLines lines{};
   odf::Params params{};
   odf::QuadConsts quad{};
+  odf::QuadConsts* d_quad = nullptr;   // device copy read by the Voigt kernels
   int64_t* d_goff = nullptr;        // per-bin offsets into the ODF global scratch
   int64_t gscr_elems = 0;           // scratch elements per point
 
