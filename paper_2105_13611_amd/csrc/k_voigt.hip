@@ -38,12 +38,16 @@ constexpr float kSqrtPiF = 1.77245385090551602730f;
 // waves per SIMD the FP32 kernel is compiled for (VGPR budget 512 / waves)
 constexpr int kMinWaves32 = 1;
 
-__device__ __forceinline__ int xcd_remap(int bid, int total) {
-  // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-  // contiguous range of (point, tile) so neighbouring tiles, which read the
-  // same survivors, share that XCD's L2.
-  const int per = (total + 7) / 8;
-  return (bid & 7) * per + (bid >> 3);
+// Workgroup order.  The hardware deals consecutive workgroups round-robin
+// to the 8 XCDs, so consecutive tiles of a point land on different XCDs and
+// every XCD gets an equal share of every point.  (Giving each XCD a
+// contiguous range of points instead would let one expensive point -- costs
+// differ by two orders of magnitude across the T-P grid -- idle the other
+// XCDs; the survivors a tile reads are a few MB per point, so L2 sharing
+// between neighbouring tiles is not worth that imbalance.)
+__device__ __forceinline__ int tile_order(int bid, int total) {
+  (void)total;
+  return bid;
 }
 
 __device__ __forceinline__ void kahan_add(float& s, float& c, float v) {
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
                                                  int tiles_per_point, int total) {
   __shared__ float lds_p[kWavesPerWG][kWavePoints];   // partial sums of core/ring rows
   __shared__ float lds_c[kWavesPerWG][kWavePoints];   // Kahan compensations
-  const int logical = xcd_remap(blockIdx.x, total);
+  const int logical = tile_order(blockIdx.x, total);
   if (logical >= total) return;
   const int pt = logical / tiles_per_point;
   const int tile = logical - pt * tiles_per_point;
@@ -492,7 +496,7 @@ __device__ __forceinline__ void line64(const Line64& l, int t_lo, int t_hi, int 
 __global__ __launch_bounds__(256) void k_voigt64(Params P, Batch B, const QuadConsts* __restrict__ Q,
                                                  int tiles_per_point, int total) {
   __shared__ double lds_s[kWavesPerWG][kWavePoints];
-  const int logical = xcd_remap(blockIdx.x, total);
+  const int logical = tile_order(blockIdx.x, total);
   if (logical >= total) return;
   const int p = logical / tiles_per_point;
   const int tile = logical - p * tiles_per_point;
