@@ -29,9 +29,9 @@ sys.path.insert(0, ROOT)
 METRIC = "ODF (T,P) points/s + line evals/s, FP32 vs FP64 plain at ≤1e-3 ODF err"
 
 # nominal FP32 operations per Voigt sample on the far-wing path (the path
-# almost every sample takes): index->d 1, x(d) 5, x^2 1, u 1, denominator 3,
-# reciprocal 1, scale 2, Kahan update 4
-FLOP_PER_SAMPLE_F32 = 18
+# almost every sample takes), FMA = 2: x from the index 5, x^2 1, numerator
+# 2, denominator 3, reciprocal 1, product 1, compensated add 4
+FLOP_PER_SAMPLE_F32 = 17
 # FP64 path: x(d) 16, x^2 1, r 1, four GH pairs 4*(1+3)+3*3, division 1,
 # scale 3, accumulate 1
 FLOP_PER_SAMPLE_F64 = 48
