@@ -91,6 +91,8 @@ __global__ void k_point_state(Params P, Batch B) {
     ps.rho = rho;
     ps.pad = 0.0;
     B.state[p] = ps;
+    B.hmax[p] = 0;
+    B.nsamp[p] = 0ull;
   }
   const double saha = pow(2.0 * kPi * kMe * kK / (kH * kH), 1.5);
   const double vt = B.vt_kms[p] * 1e5;
@@ -124,37 +126,71 @@ hipError_t launch_point_state(hipStream_t st, const Params& P, const Batch& B) {
   return hipGetLastError();
 }
 
+// Per-line constants, loaded once and reused for every point of a batch.
+struct LineData {
+  double j0s, amp, e_k, hc_k, g_rad, g_stark, g_vdw, thr;
+  int32_t sp, ss;
+};
+
+__device__ __forceinline__ LineData load_line(const DevLines& L, int64_t i) {
+  LineData d;
+  d.j0s = L.j0s[i];
+  d.amp = L.amp[i];
+  d.e_k = L.e_k[i];
+  d.hc_k = L.hc_k[i];
+  d.g_rad = L.g_rad[i];
+  d.g_stark = L.g_stark[i];
+  d.g_vdw = L.g_vdw[i];
+  d.thr = L.thr[i];
+  d.sp = L.sp[i];
+  d.ss = L.ss[i];
+  return d;
+}
+
+// Factors of a line that depend on T only (shared by the pressures of a T).
+struct TFactors {
+  double T = -1.0;
+  double stim = 0.0, boltz = 0.0;
+  __device__ __forceinline__ void update(const LineData& d, double t) {
+    if (t == T) return;
+    T = t;
+    stim = -expm1(-d.hc_k / t);
+    boltz = exp(-d.e_k / t);
+  }
+};
+
 struct LineEval {
   double S, a, b;
   int32_t jlo, jhi;
   bool surv;
 };
 
-// Strength, damping, selection and window of sorted line i at one point.
-__device__ __forceinline__ LineEval eval_line(const Params& P, const DevLines& L, int64_t i,
-                                              const PointState& ps, const double* __restrict__ pop,
+// Strength, damping, selection and window of one line at one point.  The
+// keep test S H(0,a) >= thr is skipped when S < thr already decides it
+// (H(0,a) = erfcx(a) <= 1 for a >= 0).
+__device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d,
+                                              const PointState& ps, const TFactors& tf,
+                                              const double* __restrict__ pop,
                                               const double* __restrict__ bT) {
   LineEval e;
-  const double T = ps.T;
-  const double b = bT[L.sp[i]];
-  const double stim = -expm1(-L.hc_k[i] / T);
-  const double boltz = exp(-L.e_k[i] / T);
-  const double S = L.amp[i] * pop[L.ss[i]] * boltz * stim / b;
-  const double a = (L.g_rad[i] + L.g_stark[i] * ps.cS + L.g_vdw[i] * ps.cW) / b;
-  const double thr = L.thr[i];
+  const double b = bT[d.sp];
+  const double S = d.amp * pop[d.ss] * tf.boltz * tf.stim / b;
+  const double thr = d.thr;
   e.S = S;
-  e.a = a;
   e.b = b;
+  e.a = 0.0;
   e.surv = false;
   e.jlo = 0;
   e.jhi = -1;
+  if (!(S >= thr)) return e;
+  const double a = (d.g_rad + d.g_stark * ps.cS + d.g_vdw * ps.cW) / b;
+  e.a = a;
   if (!(S * erfcx(a) >= thr)) return e;
   const double xg = sqrt(fmax(0.0, log(2.0 * S / thr)));
   const double xl = sqrt(2.0 * S * a / (kSqrtPi * thr));
   const double xw = fmin(P.cap, fmax(xg, xl));
-  const double j0 = L.j0s[i];
-  const double lo = ceil(j0 - log1p(xw * b) / P.lnq);
-  const double hi = floor(j0 - log1p(-xw * b) / P.lnq);
+  const double lo = ceil(d.j0s - log1p(xw * b) / P.lnq);
+  const double hi = floor(d.j0s - log1p(-xw * b) / P.lnq);
   const double jl = fmax(lo, 0.0);
   const double jh = fmin(hi, (double)(P.N - 1));
   if (jl > jh) return e;
@@ -164,25 +200,76 @@ __device__ __forceinline__ LineEval eval_line(const Params& P, const DevLines& L
   return e;
 }
 
+constexpr int kWavesK1 = kLineBlock / 64;
+
+// Selection: one thread per line, looping over the batch's points so the
+// line's constants are read once per batch.  Writes the keep flags, the
+// per-(point, block) survivor counts, and per point the largest half-window
+// and the number of Voigt samples.
 __global__ __launch_bounds__(kLineBlock) void k_select(Params P, DevLines L, Batch B) {
-  const int p = blockIdx.y;
+  __shared__ int32_t wc[kMaxBatch][kWavesK1];
+  __shared__ int32_t wh[kMaxBatch][kWavesK1];
+  __shared__ unsigned long long wn[kMaxBatch][kWavesK1];
   const int64_t i = (int64_t)blockIdx.x * kLineBlock + threadIdx.x;
   const int64_t nblk = gridDim.x;
-  const PointState ps = B.state[p];
-  bool s = false;
-  if (i < L.n) {
-    s = eval_line(P, L, i, ps, B.pop + (int64_t)p * P.n_species * P.n_stages,
-                  B.bT + (int64_t)p * P.n_species).surv;
-    B.flags[(int64_t)p * B.rec_stride + i] = s ? 1 : 0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const bool valid = i < L.n;
+  LineData d{};
+  if (valid) d = load_line(L, i);
+  const int32_t J = (int32_t)rint(d.j0s);
+  TFactors tf;
+  const int np = B.n_points;
+  for (int p = 0; p < np; ++p) {
+    const PointState ps = B.state[p];
+    bool s = false;
+    int32_t half = 0;
+    unsigned long long ns = 0;
+    if (valid) {
+      tf.update(d, ps.T);
+      const LineEval e = eval_line(P, d, ps, tf, B.pop + (int64_t)p * P.n_species * P.n_stages,
+                                   B.bT + (int64_t)p * P.n_species);
+      s = e.surv;
+      B.flags[(int64_t)p * B.rec_stride + i] = s ? 1 : 0;
+      if (s) {
+        half = max(J - e.jlo, e.jhi - J) + 1;
+        ns = (unsigned long long)(e.jhi - e.jlo + 1);
+      }
+    }
+    const unsigned long long m = __ballot(s);
+    if (m) {
+      for (int o = 32; o > 0; o >>= 1) {
+        half = max(half, __shfl_xor(half, o, 64));
+        ns += __shfl_xor(ns, o, 64);
+      }
+    }
+    if (lane == 0) {
+      wc[p][wid] = __popcll(m);
+      wh[p][wid] = half;
+      wn[p][wid] = ns;
+    }
   }
-  const int cnt = __syncthreads_count(s);
-  if (threadIdx.x == 0) B.blk[(int64_t)p * nblk + blockIdx.x] = cnt;
+  __syncthreads();
+  for (int p = threadIdx.x; p < np; p += blockDim.x) {
+    int32_t c = 0, h = 0;
+    unsigned long long n = 0;
+    for (int w = 0; w < kWavesK1; ++w) {
+      c += wc[p][w];
+      h = max(h, wh[p][w]);
+      n += wn[p][w];
+    }
+    B.blk[(int64_t)p * nblk + blockIdx.x] = c;
+    if (n) {
+      atomicMax(B.hmax + p, h);
+      atomicAdd(B.nsamp + p, n);
+    }
+  }
 }
 
 hipError_t launch_select(hipStream_t st, const Params& P, const DevLines& L, const Batch& B) {
   if (B.n_points == 0 || L.n == 0) return hipSuccess;
+  if (B.n_points > kMaxBatch) return hipErrorInvalidValue;
   const int64_t nblk = n_line_blocks(L.n);
-  hipLaunchKernelGGL(k_select, dim3((unsigned)nblk, B.n_points), dim3(kLineBlock), 0, st, P, L, B);
+  hipLaunchKernelGGL(k_select, dim3((unsigned)nblk), dim3(kLineBlock), 0, st, P, L, B);
   return hipGetLastError();
 }
 
@@ -221,11 +308,7 @@ __global__ __launch_bounds__(1024) void k_scan(Batch B, int64_t nblk) {
     if (threadIdx.x == 1023) carry = excl + v;
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    B.nsurv[p] = carry;
-    B.hmax[p] = 0;
-    B.nsamp[p] = 0ull;
-  }
+  if (threadIdx.x == 0) B.nsurv[p] = carry;
 }
 
 hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const Batch& B) {
@@ -237,32 +320,42 @@ hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const
 
 // Survivor emission: the intra-block prefix of the flags gives each kept
 // line its slot after the block's offset, so the survivor list keeps the
-// wavelength order (stable compaction, no atomics on positions).
+// wavelength order (stable compaction, no atomics on positions).  One thread
+// per line, looping over the batch's points.
 template <bool kRec64>
 __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch B) {
-  __shared__ int32_t wcnt[kLineBlock / 64];
-  __shared__ int32_t red_h[kLineBlock / 64];
-  __shared__ unsigned long long red_n[kLineBlock / 64];
-  const int p = blockIdx.y;
+  __shared__ int32_t wc[kMaxBatch][kWavesK1];
   const int64_t i = (int64_t)blockIdx.x * kLineBlock + threadIdx.x;
   const int64_t nblk = gridDim.x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const bool f = (i < L.n) && B.flags[(int64_t)p * B.rec_stride + i];
-  const unsigned long long m = __ballot(f);
-  if (lane == 0) wcnt[wid] = __popcll(m);
+  const bool valid = i < L.n;
+  const int np = B.n_points;
+  unsigned long long mine = 0;   // bit p: this line survives at point p
+  for (int p = 0; p < np; ++p) {
+    const bool f = valid && B.flags[(int64_t)p * B.rec_stride + i];
+    if (f) mine |= 1ull << p;
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) wc[p][wid] = __popcll(m);
+  }
   __syncthreads();
-  int32_t off = B.blk[(int64_t)p * nblk + blockIdx.x];
-  for (int w = 0; w < wid; ++w) off += wcnt[w];
-  const unsigned long long below = (lane == 0) ? 0ull : (m & (~0ull >> (64 - lane)));
-  off += __popcll(below);
-  int32_t half = 0;
-  unsigned long long ns = 0;
-  if (f) {
+  if (!__ballot(mine != 0ull)) return;
+  LineData d{};
+  if (valid) d = load_line(L, i);
+  TFactors tf;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int p = 0; p < np; ++p) {
+    const bool f = (mine >> p) & 1ull;
+    const unsigned long long m = __ballot(f);
+    if (!m) continue;
+    if (!f) continue;
+    int32_t off = B.blk[(int64_t)p * nblk + blockIdx.x];
+    for (int w = 0; w < wid; ++w) off += wc[p][w];
+    off += __popcll(m & below);
     const PointState ps = B.state[p];
-    const LineEval e = eval_line(P, L, i, ps, B.pop + (int64_t)p * P.n_species * P.n_stages,
+    tf.update(d, ps.T);
+    const LineEval e = eval_line(P, d, ps, tf, B.pop + (int64_t)p * P.n_species * P.n_stages,
                                  B.bT + (int64_t)p * P.n_species);
-    const double j0 = L.j0s[i];
-    const double Jd = rint(j0);
+    const double Jd = rint(d.j0s);
     const int32_t J = (int32_t)Jd;
     const int64_t slot = (int64_t)p * B.rec_stride + off;
     const double c1 = P.lnq / e.b;
@@ -282,7 +375,7 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
       r.czh = czh;
       r.li = (int32_t)i;
       r.pad0 = r.pad1 = r.pad2 = 0;
-      r.phi = j0 - Jd;
+      r.phi = d.j0s - Jd;
       r.S = e.S;
       r.y = e.a;
       r.c1 = c1;
@@ -293,35 +386,11 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
       r.jlo = e.jlo;
       r.jhi = e.jhi;
       r.czh = czh;
-      r.phi = (float)(j0 - Jd);
+      r.phi = (float)(d.j0s - Jd);
       r.c1 = (float)c1;
       r.C1 = (float)(e.S * e.a / kSqrtPi);
       r.y = (float)e.a;
       reinterpret_cast<Rec32*>(B.rec)[slot] = r;
-    }
-    half = max(J - e.jlo, e.jhi - J) + 1;
-    ns = (unsigned long long)(e.jhi - e.jlo + 1);
-  }
-  // block reductions, then one atomic per block (integers: order-free)
-  for (int o = 32; o > 0; o >>= 1) {
-    half = max(half, __shfl_xor(half, o, 64));
-    ns += __shfl_xor(ns, o, 64);
-  }
-  if (lane == 0) {
-    red_h[wid] = half;
-    red_n[wid] = ns;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int32_t h = 0;
-    unsigned long long n = 0;
-    for (int w = 0; w < kLineBlock / 64; ++w) {
-      h = max(h, red_h[w]);
-      n += red_n[w];
-    }
-    if (n) {
-      atomicMax(B.hmax + p, h);
-      atomicAdd(B.nsamp + p, n);
     }
   }
 }
@@ -329,13 +398,12 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
 hipError_t launch_emit(hipStream_t st, const Params& P, const DevLines& L, const Batch& B,
                        int rec64) {
   if (B.n_points == 0 || L.n == 0) return hipSuccess;
+  if (B.n_points > kMaxBatch) return hipErrorInvalidValue;
   const int64_t nblk = n_line_blocks(L.n);
   if (rec64)
-    hipLaunchKernelGGL(k_emit<true>, dim3((unsigned)nblk, B.n_points), dim3(kLineBlock), 0, st, P,
-                       L, B);
+    hipLaunchKernelGGL(k_emit<true>, dim3((unsigned)nblk), dim3(kLineBlock), 0, st, P, L, B);
   else
-    hipLaunchKernelGGL(k_emit<false>, dim3((unsigned)nblk, B.n_points), dim3(kLineBlock), 0, st,
-                       P, L, B);
+    hipLaunchKernelGGL(k_emit<false>, dim3((unsigned)nblk), dim3(kLineBlock), 0, st, P, L, B);
   return hipGetLastError();
 }
 

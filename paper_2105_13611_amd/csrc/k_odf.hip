@@ -66,12 +66,13 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 template <typename T, typename K>
 __global__ __launch_bounds__(kOdfThreads) void k_odf(Params P, const T* __restrict__ kappa,
                                                      int64_t kappa_stride, T* __restrict__ out,
+                                                     const int32_t* __restrict__ bins,
                                                      int lds_cap, K* __restrict__ gscratch,
                                                      const int64_t* __restrict__ goff,
                                                      int64_t gscratch_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kOdfThreads / 64];
-  const int b = blockIdx.x, p = blockIdx.y;
+  const int b = bins[blockIdx.x], p = blockIdx.y;
   const int64_t e0 = P.edges[b], e1 = P.edges[b + 1];
   const int n = (int)(e1 - e0);
   int npow2 = 1;
@@ -123,32 +124,39 @@ __global__ __launch_bounds__(kOdfThreads) void k_odf(Params P, const T* __restri
 }  // namespace
 
 hipError_t launch_odf(hipStream_t st, const Params& P, const void* kappa, int64_t kappa_stride,
-                      int32_t n_points, void* out, int max_bin, void* gscratch,
+                      int32_t n_points, void* out, const OdfClasses& C, void* gscratch,
                       const int64_t* goff, int64_t gscratch_stride) {
   if (n_points == 0 || P.n_bins == 0) return hipSuccess;
-  int npow2 = 1;
-  while (npow2 < max_bin) npow2 <<= 1;
   const int key_bytes = P.precision == 1 ? 4 : 8;
-  const int lds_cap = (128 * 1024) / key_bytes;
-  const int lds_elems = npow2 <= lds_cap ? npow2 : lds_cap;
-  const size_t shmem = (size_t)lds_elems * key_bytes;
-  dim3 grid(P.n_bins, n_points);
-  if (P.precision == 1) {
-    auto k = k_odf<float, uint32_t>;
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)shmem);
+  const int lds_cap = odf_lds_cap(P.precision);
+  // one launch per bin-size class, each with the LDS its largest bin needs
+  for (int c = 0; c < C.n_classes; ++c) {
+    const int cnt = C.count[c];
+    if (cnt == 0) continue;
+    const int npow2 = C.npow2[c];
+    const size_t shmem = npow2 <= lds_cap ? (size_t)npow2 * key_bytes : 0;
+    dim3 grid(cnt, n_points);
+    const int32_t* bins = C.bins + C.offset[c];
+    if (P.precision == 1) {
+      auto k = k_odf<float, uint32_t>;
+      hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)(lds_cap * key_bytes));
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, grid, dim3(kOdfThreads), shmem, st, P, (const float*)kappa, kappa_stride,
+                         (float*)out, bins, lds_cap, (uint32_t*)gscratch, goff, gscratch_stride);
+    } else {
+      auto k = k_odf<double, uint64_t>;
+      hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)(lds_cap * key_bytes));
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, grid, dim3(kOdfThreads), shmem, st, P, (const double*)kappa,
+                         kappa_stride, (double*)out, bins, lds_cap, (uint64_t*)gscratch, goff,
+                         gscratch_stride);
+    }
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, grid, dim3(kOdfThreads), shmem, st, P, (const float*)kappa, kappa_stride,
-                       (float*)out, lds_cap, (uint32_t*)gscratch, goff, gscratch_stride);
-  } else {
-    auto k = k_odf<double, uint64_t>;
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)shmem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, grid, dim3(kOdfThreads), shmem, st, P, (const double*)kappa, kappa_stride,
-                       (double*)out, lds_cap, (uint64_t*)gscratch, goff, gscratch_stride);
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace odf

@@ -26,6 +26,7 @@ constexpr int kWavePoints = kWave * kRows;       // 1024 fine points per wave
 constexpr int kWavesPerWG = 4;
 constexpr int kWGPoints = kWavePoints * kWavesPerWG;  // 4096 per workgroup
 constexpr int kLineBlock = 256;                  // lines per workgroup in K1
+constexpr int kMaxBatch = 64;                    // points per device batch (bit masks in K1)
 
 // ---- Voigt region constants -----------------------------------------------
 // FP32: rows of 64 fine points are classified by the smallest |x| in them:
@@ -159,8 +160,19 @@ hipError_t launch_select(hipStream_t st, const Params& P, const DevLines& L, con
 hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const Batch& B);
 hipError_t launch_emit(hipStream_t st, const Params& P, const DevLines& L, const Batch& B, int rec64);
 hipError_t launch_voigt(hipStream_t st, const Params& P, const Batch& B, const QuadConsts* Q);
+// Bins grouped by padded size (power of two) so each ODF launch reserves only
+// the LDS its largest bin needs.  bins: device list of bin indices, class c at
+// [offset[c], offset[c] + count[c]).
+constexpr int kMaxOdfClasses = 32;
+struct OdfClasses {
+  int n_classes;
+  int npow2[kMaxOdfClasses];
+  int offset[kMaxOdfClasses];
+  int count[kMaxOdfClasses];
+  const int32_t* bins;
+};
 hipError_t launch_odf(hipStream_t st, const Params& P, const void* kappa, int64_t kappa_stride,
-                      int32_t n_points, void* out, int max_bin, void* gscratch,
+                      int32_t n_points, void* out, const OdfClasses& C, void* gscratch,
                       const int64_t* goff, int64_t gscratch_stride);
 // largest bin (in points) that the ODF kernel sorts in LDS
 inline int odf_lds_cap(int precision) { return (128 * 1024) / (precision == 1 ? 4 : 8); }

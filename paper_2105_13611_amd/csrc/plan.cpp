@@ -264,7 +264,7 @@ odf_status enqueue_batch(odf_plan_s* p, const Batch& B, char* slot_base, const S
   { TimedLaunch tl(timer, st, 4); HIP_TRY(launch_voigt(st, p->params, B, p->d_quad)); }
   if (out) {
     TimedLaunch tl(timer, st, 5);
-    HIP_TRY(launch_odf(st, p->params, B.kappa, B.kappa_stride, B.n_points, out, p->max_bin,
+    HIP_TRY(launch_odf(st, p->params, B.kappa, B.kappa_stride, B.n_points, out, p->odf_classes,
                        slot_base + s.off_gscr, p->d_goff, p->gscr_elems));
   }
   return ODF_OK;
@@ -439,6 +439,38 @@ odf_status odf_plan(const odf_lines* lines, const odf_species* species, const od
     double *mass, *chi, *part, *Fc;
     int64_t* edges;
     const int S = p->n_species, K = p->n_stages;
+    // bins grouped by padded size for the ODF launches
+    std::vector<int32_t> order;
+    {
+      std::map<int, std::vector<int32_t>> cls;
+      for (int b = 0; b < p->n_bins; ++b) {
+        int64_t n = p->edges[b + 1] - p->edges[b], pw = 1;
+        while (pw < n) pw <<= 1;
+        cls[(int)pw].push_back(b);
+      }
+      if ((int)cls.size() > kMaxOdfClasses) {
+        set_error("layout: too many distinct bin sizes");
+        free_owned(pp);
+        return ODF_E_INVALID;
+      }
+      OdfClasses& C = pp->odf_classes;
+      C.n_classes = 0;
+      for (auto& kv : cls) {
+        C.npow2[C.n_classes] = kv.first;
+        C.offset[C.n_classes] = (int)order.size();
+        C.count[C.n_classes] = (int)kv.second.size();
+        order.insert(order.end(), kv.second.begin(), kv.second.end());
+        ++C.n_classes;
+      }
+    }
+    int32_t* binlist = nullptr;
+    if ((st = dev_alloc(pp, &binlist, std::max<int64_t>(p->n_bins, 1)))) { free_owned(pp); return st; }
+    pp->odf_classes.bins = binlist;
+    if (hipMemcpy(binlist, order.data(), order.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("bin list upload failed");
+      free_owned(pp);
+      return ODF_E_DEVICE;
+    }
     if ((st = dev_alloc(pp, &mass, S)) || (st = dev_alloc(pp, &chi, std::max(S * (K - 1), 1))) ||
         (st = dev_alloc(pp, &part, S * K)) || (st = dev_alloc(pp, &Fc, p->n_steps + 1)) ||
         (st = dev_alloc(pp, &edges, p->n_bins + 1)) ||
@@ -503,7 +535,7 @@ odf_status odf_plan(const odf_lines* lines, const odf_species* species, const od
     return ODF_E_NOMEM;
   }
   int32_t pts = (int32_t)std::min<int64_t>(
-      (p->opts.workspace_bytes - p->fixed_bytes) / std::max<int64_t>(p->per_point_bytes, 1), 64);
+      (p->opts.workspace_bytes - p->fixed_bytes) / std::max<int64_t>(p->per_point_bytes, 1), kMaxBatch);
   if (p->opts.max_batch_points > 0) pts = std::min(pts, p->opts.max_batch_points);
   while (pts > 1 && make_slot(p.get(), pts).bytes > p->opts.workspace_bytes) --pts;
   p->compute_points = std::max(pts, 1);
@@ -684,7 +716,7 @@ odf_status odf_stage_reduce(odf_plan_t* p, const void* kappa_dev, void* out_dev)
   WorkspaceLease lease(p->loop.get());
   hipStream_t s = static_cast<hipStream_t>(p->opts.stream);
   char* base = static_cast<char*>(p->opts.workspace);
-  HIP_TRY(launch_odf(s, p->params, kappa_dev, p->N, 1, out_dev, p->max_bin,
+  HIP_TRY(launch_odf(s, p->params, kappa_dev, p->N, 1, out_dev, p->odf_classes,
                      base + p->compute_slot.off_gscr, p->d_goff, p->gscr_elems));
   HIP_TRY(hipStreamSynchronize(s));
   return ODF_OK;

@@ -64,6 +64,7 @@ struct odf_plan_s {
   odf::QuadConsts quad{};
   odf::QuadConsts* d_quad = nullptr;   // device copy read by the Voigt kernels
   int64_t* d_goff = nullptr;        // per-bin offsets into the ODF global scratch
+  odf::OdfClasses odf_classes{};    // bins grouped by padded size
   int64_t gscr_elems = 0;           // scratch elements per point
 
   // workspace carving
