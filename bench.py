@@ -60,13 +60,13 @@ def stratified_points(points, n, seed=2):
     return np.array(sorted(set(idx[:n])), dtype=np.int64)
 
 
-def run_gpu(w, precision, steps, warmup, workspace_gb, points_idx=None):
+def run_gpu(w, precision, steps, warmup, workspace_gb, points_idx=None, batch_points=0):
     import torch
     from paper_2105_13611_amd import odf
     pts = w.points if points_idx is None else w.points.take(points_idx)
     t0 = time.perf_counter()
     plan = odf.plan_for(w, precision=precision, workspace_bytes=int(workspace_gb * (1 << 30)),
-                        kernel_timing=True)
+                        kernel_timing=True, max_batch_points=batch_points)
     t_plan = time.perf_counter() - t0
     out = plan.new_out(pts.n_points)
     for k in range(warmup):
@@ -158,14 +158,72 @@ def _cpu_task(args):
     return dict(point=i, t_lines=t_lines, t_bins=t_bins, samples_total=total, samples_bins=nsb)
 
 
+def run_serving(n_requests, rate_hz, workspace_gb, max_points):
+    """Continuous-batching run on the Poisson request stream of the serving
+    workload: each request has its own composition ([M/H], [alpha/Fe]) and a
+    random subset of the T-P grid, over the shared resident line list and
+    bins (mixed precision).  Requests are submitted at their arrival times;
+    latency is t_done - arrival."""
+    import numpy as np
+    import torch
+    from paper_2105_13611_amd import odf
+    from paper_2105_13611_amd import workload as W
+    w = W.config(4, n_requests=n_requests)
+    reqs = w.requests
+    if rate_hz:
+        reqs = W.draw_requests_cfg4(4, w.species, w.points, n_requests, rate_hz=rate_hz)
+    if max_points:
+        reqs = [W.Request(r.abundance, r.points.take(np.arange(min(max_points, r.points.n_points))),
+                          r.arrival_s) for r in reqs]
+    plan = odf.plan_for(w, precision="mixed", workspace_bytes=int(workspace_gb * (1 << 30)))
+    outs = [plan.new_out(r.points.n_points) for r in reqs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tickets = []
+    for r, o in zip(reqs, outs):
+        delay = r.arrival_s - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append((plan.submit(r.abundance, r.points, o)[0], time.perf_counter()))
+    stats = []
+    for (t, t_sub), r in zip(tickets, reqs):
+        st = plan.wait(t, 3600.0)
+        stats.append(st)
+        log(f"[serve] request {t}: {r.points.n_points} points, {st['state']}, "
+            f"latency {st['t_done'] - st['t_submit']:.2f} s")
+    wall = time.perf_counter() - t0
+    lat = np.array([s["t_done"] - s["t_submit"] for s in stats])
+    wait = np.array([s["t_admit"] - s["t_submit"] for s in stats])
+    pts = sum(r.points.n_points for r in reqs)
+    span = max(s["t_done"] for s in stats) - min(s["t_submit"] for s in stats)
+    res = dict(metric="ODF serving: latency percentiles and points/s under a Poisson request stream",
+               mode="serve", requests=len(reqs), rate_hz=rate_hz or 20.0,
+               offered_points_per_s=pts / max(reqs[-1].arrival_s, 1e-9),
+               achieved_points_per_s=pts / span, wall_s=wall,
+               latency_s=dict(p50=float(np.percentile(lat, 50)), p95=float(np.percentile(lat, 95)),
+                              p99=float(np.percentile(lat, 99)), max=float(lat.max())),
+               admission_wait_s=dict(p50=float(np.percentile(wait, 50)), max=float(wait.max())),
+               points=pts, failed=sum(s["state"] != "DONE" for s in stats),
+               slots=None, dtype="f32", data="synthetic",
+               config={"workload": "serving stream over the 1e7-line table: per-request composition "
+                                   "and 1..1425 T-P points at vturb 2 km/s, 1212 bins x 12 sub-bins"})
+    plan.destroy()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", choices=["table", "serve"], default="table")
+    ap.add_argument("--serve-requests", type=int, default=12)
+    ap.add_argument("--serve-rate", type=float, default=0.0, help="req/s (0 = the stream's 20 req/s)")
+    ap.add_argument("--serve-max-points", type=int, default=0)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--points", type=int, default=0, help="stratified subset (0 = whole table)")
     ap.add_argument("--workspace-gb", type=float, default=40.0)
+    ap.add_argument("--batch-points", type=int, default=0, help="points per device batch (0 = automatic)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0)
     args = ap.parse_args()
@@ -175,6 +233,10 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.mode == "serve":
+        print(json.dumps(run_serving(args.serve_requests, args.serve_rate, args.workspace_gb,
+                                     args.serve_max_points)), flush=True)
+        return
     from paper_2105_13611_amd import workload as W
     t0 = time.perf_counter()
     w = W.config(2)
@@ -185,7 +247,7 @@ def main():
     res = {}
     for p in precs:
         res[p] = run_gpu(w, p, args.steps, args.warmup if p == precs[0] else min(args.warmup, 1),
-                         args.workspace_gb, idx)
+                         args.workspace_gb, idx, args.batch_points)
         r = res[p]
         log(f"[bench] {p}: {r['n_points'] * r['steps'] / r['seconds']:.2f} points/s, "
             f"stage ms {r['stage_ms']}, plan {r['plan_seconds']:.1f} s")

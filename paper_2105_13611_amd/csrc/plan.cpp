@@ -540,6 +540,24 @@ odf_status odf_plan(const odf_lines* lines, const odf_species* species, const od
   while (pts > 1 && make_slot(p.get(), pts).bytes > p->opts.workspace_bytes) --pts;
   p->compute_points = std::max(pts, 1);
   p->compute_slot = make_slot(p.get(), p->compute_points);
+  // two lanes of half the points when the workspace holds two slots of >= 8 points
+  if (p->compute_points >= 16) {
+    const SlotLayout half = make_slot(p.get(), p->compute_points / 2);
+    if (2 * half.bytes <= p->opts.workspace_bytes) {
+      bool ok = true;
+      for (int k = 0; k < 2 && ok; ++k)
+        ok = hipStreamCreateWithFlags(&p->lane_stream[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&p->ev_join[k], hipEventDisableTiming) == hipSuccess;
+      ok = ok && hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess;
+      if (!ok) {
+        set_error("stream or event creation failed");
+        free_owned(p.get());
+        return ODF_E_DEVICE;
+      }
+      p->compute_lanes = 2;
+      p->lane_slot = half;
+    }
+  }
   p->loop.reset(new RequestLoop(p.get()));
   *out = p.release();
   return ODF_OK;
@@ -567,6 +585,12 @@ odf_status odf_plan_destroy(odf_plan_t* plan) {
   plan->loop.reset();  // drains and joins the request loop
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : plan->timer.pool) (void)hipEventDestroy(e);
+  for (int k = 0; k < 2; ++k) {
+    if (plan->lane_stream[k]) (void)hipStreamDestroy(plan->lane_stream[k]);
+    if (plan->ev_join[k]) (void)hipEventDestroy(plan->ev_join[k]);
+  }
+  if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+  if (plan->pinned) (void)hipHostFree(plan->pinned);
   free_owned(plan);
   delete plan;
   return ODF_OK;
@@ -582,23 +606,61 @@ odf_status odf_compute(odf_plan_t* p, const odf_request* r, odf_stats* stats) {
   WorkspaceLease lease(p->loop.get());   // the request loop is idle while this runs
   hipStream_t s = static_cast<hipStream_t>(p->opts.stream);
   char* base = static_cast<char*>(p->opts.workspace);
-  const SlotLayout& sl = p->compute_slot;
+  const int lanes = p->compute_lanes;
+  const SlotLayout& sl = lanes == 2 ? p->lane_slot : p->compute_slot;
   const int n = r->n_points;
-  std::vector<int32_t> h_nsurv(std::max(n, 1));
-  std::vector<unsigned long long> h_nsamp(std::max(n, 1));
-  HIP_TRY(hipMemcpyAsync(base + sl.off_abund, r->abundance, 8 * p->n_species, hipMemcpyHostToDevice, s));
+  const int S = p->n_species;
+  // pinned host staging: point arrays and abundances in, counters out
+  const size_t need = (size_t)8 * (3 * (size_t)n + S) + 12 * (size_t)std::max(n, 1) + 64;
+  if (p->pinned_bytes < need) {
+    if (p->pinned) (void)hipHostFree(p->pinned);
+    p->pinned = nullptr;
+    p->pinned_bytes = 0;
+    HIP_TRY(hipHostMalloc(&p->pinned, need, hipHostMallocDefault));
+    p->pinned_bytes = need;
+  }
+  double* hT = static_cast<double*>(p->pinned);
+  double* hP = hT + n;
+  double* hV = hP + n;
+  double* hA = hV + n;
+  unsigned long long* h_nsamp = reinterpret_cast<unsigned long long*>(hA + S);
+  int32_t* h_nsurv = reinterpret_cast<int32_t*>(h_nsamp + std::max(n, 1));
+  std::memcpy(hT, r->T_K, 8 * (size_t)n);
+  std::memcpy(hP, r->log10_P_cgs, 8 * (size_t)n);
+  std::memcpy(hV, r->vturb_kms, 8 * (size_t)n);
+  std::memcpy(hA, r->abundance, 8 * (size_t)S);
+  hipStream_t ls[2] = {s, s};
+  if (lanes == 2) {
+    HIP_TRY(hipEventRecord(p->ev_fork, s));
+    for (int k = 0; k < 2; ++k) {
+      ls[k] = p->lane_stream[k];
+      HIP_TRY(hipStreamWaitEvent(ls[k], p->ev_fork, 0));
+    }
+  }
+  for (int k = 0; k < lanes; ++k)
+    HIP_TRY(hipMemcpyAsync(base + k * sl.bytes + sl.off_abund, hA, 8 * S, hipMemcpyHostToDevice, ls[k]));
   const size_t osz = (p->opts.precision == ODF_PREC_MIXED ? 4 : 8);
-  for (int b0 = 0; b0 < n; b0 += sl.points) {
+  int batch = 0;
+  for (int b0 = 0; b0 < n; b0 += sl.points, ++batch) {
+    const int k = batch % lanes;
+    hipStream_t lst = ls[k];
+    char* sb = base + k * sl.bytes;
     const int nb = std::min(sl.points, n - b0);
-    HIP_TRY(hipMemcpyAsync(base + sl.off_T, r->T_K + b0, 8 * nb, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(base + sl.off_logP, r->log10_P_cgs + b0, 8 * nb, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(base + sl.off_vt, r->vturb_kms + b0, 8 * nb, hipMemcpyHostToDevice, s));
-    Batch B = make_batch(p, sl, base, nb);
+    HIP_TRY(hipMemcpyAsync(sb + sl.off_T, hT + b0, 8 * nb, hipMemcpyHostToDevice, lst));
+    HIP_TRY(hipMemcpyAsync(sb + sl.off_logP, hP + b0, 8 * nb, hipMemcpyHostToDevice, lst));
+    HIP_TRY(hipMemcpyAsync(sb + sl.off_vt, hV + b0, 8 * nb, hipMemcpyHostToDevice, lst));
+    Batch B = make_batch(p, sl, sb, nb);
     char* outp = static_cast<char*>(r->out) + (size_t)b0 * p->n_bins * p->n_steps * osz;
-    if ((st = enqueue_batch(p, B, base, sl, outp, s, p->opts.kernel_timing ? &p->timer : nullptr)) != ODF_OK)
-      return st;
-    HIP_TRY(hipMemcpyAsync(h_nsurv.data() + b0, B.nsurv, 4 * nb, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(h_nsamp.data() + b0, B.nsamp, 8 * nb, hipMemcpyDeviceToHost, s));
+    odf_status es = enqueue_batch(p, B, sb, sl, outp, lst, p->opts.kernel_timing ? &p->timer : nullptr);
+    if (es != ODF_OK) return es;
+    HIP_TRY(hipMemcpyAsync(h_nsurv + b0, B.nsurv, 4 * nb, hipMemcpyDeviceToHost, lst));
+    HIP_TRY(hipMemcpyAsync(h_nsamp + b0, B.nsamp, 8 * nb, hipMemcpyDeviceToHost, lst));
+  }
+  if (lanes == 2) {
+    for (int k = 0; k < 2; ++k) {
+      HIP_TRY(hipEventRecord(p->ev_join[k], ls[k]));
+      HIP_TRY(hipStreamWaitEvent(s, p->ev_join[k], 0));
+    }
   }
   HIP_TRY(hipStreamSynchronize(s));
   if (p->opts.kernel_timing) collect_timer(p->timer);

@@ -72,6 +72,16 @@ struct odf_plan_s {
   int64_t fixed_bytes = 0;
   int32_t compute_points = 0;       // points per odf_compute batch
   odf::SlotLayout compute_slot{};
+  odf::SlotLayout lane_slot{};      // slot of one lane when compute_lanes == 2
+  // odf_compute alternates batches over `compute_lanes` internal streams,
+  // each with its own slot of the workspace, forked from and joined back to
+  // options.stream, so one batch's selection and sort overlap another's
+  // Voigt kernel and launch tails
+  int32_t compute_lanes = 1;
+  hipStream_t lane_stream[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  void* pinned = nullptr;           // host staging of point arrays and counters
+  size_t pinned_bytes = 0;
 
   odf::StageTimer timer;
   std::mutex compute_mu;
