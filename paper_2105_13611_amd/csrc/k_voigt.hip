@@ -20,7 +20,10 @@
 //  - near the core, the trapezoidal rule for the same integral with the
 //    contribution of the integrand's pole at t = x + i a added in closed
 //    form (the error of the corrected rule is of order exp(-pi^2/h^2)); the
-//    node grid is shifted by half a step when x lies near a node.
+//    node grid is shifted by half a step when x lies near a node;
+//  - near the core of weakly damped lines (FP32, a < 0.4), the Taylor series
+//    of Re w in a, whose odd terms are derivatives of Dawson's function
+//    (tabulated at plan time), plus the Gaussian e^{a^2 - x^2} cos 2xa.
 // Each row of 64 points takes one of these forms for all its lanes, chosen
 // from the smallest |x| in the row, so the wave never diverges.
 // Mixed precision uses FP32 with Kahan-compensated sums (every summand is
@@ -134,6 +137,37 @@ __device__ __forceinline__ float core32(float x, float y, const QuadConsts* __re
   return v;
 }
 
+// Small-damping series (a < 0.4) for every x:
+//   H = e^{a^2 - x^2} cos(2 x a) + a sum_{k < nt} a^{2k} T_{2k+1}(x),
+// with T_n read from the cubic table in LDS at s = 1/(1 + x^2).  The number
+// of terms nt is chosen per line from a (series32_terms); relative error
+// below 1e-5 including the FP32 table (truncation dominates near a = 0.4).
+__device__ __forceinline__ int series32_terms(float y) {
+  return y < 0.004f ? 1 : (y < 0.06f ? 2 : (y < 0.2f ? 3 : 4));
+}
+
+__device__ __forceinline__ float series32(float x, float y, float y2, float y_over_pi, int nt,
+                                          const float4* __restrict__ tab) {
+  const float x2 = x * x;
+  const float t = __builtin_amdgcn_rcpf(1.0f + x2) * (float)kSerIntervals;
+  const int i = min((int)t, kSerIntervals - 1);
+  const float f = t - (float)i;
+  const float4* __restrict__ c = tab + i;
+  auto term = [&](int k) {
+    const float4 q = c[k * kSerIntervals];
+    return fmaf(fmaf(fmaf(q.w, f, q.z), f, q.y), f, q.x);
+  };
+  float U;
+  if (nt == 4) U = fmaf(fmaf(fmaf(term(3), y2, term(2)), y2, term(1)), y2, term(0));
+  else if (nt == 3) U = fmaf(fmaf(term(2), y2, term(1)), y2, term(0));
+  else if (nt == 2) U = fmaf(term(1), y2, term(0));
+  else U = term(0);
+  // cos(2 x a): the hardware cosine takes revolutions, reduced to [-1/2, 1/2]
+  const float r0 = x * y_over_pi;
+  const float g = __expf(y2 - x2) * __builtin_amdgcn_cosf(r0 - rintf(r0));
+  return fmaf(y, U, g);
+}
+
 // Line parameters broadcast to the wave (uniform values).
 struct Line32 {
   int J, jlo, jhi, czh;
@@ -215,8 +249,8 @@ __device__ __forceinline__ void inner_rows32(unsigned rows, float d0, const Far3
 
 __device__ __forceinline__ void line32(const Line32& l, int t_lo, int t_hi, int lane, float lnq2,
                                        float lnq6, float q64, float g64,
-                                       const QuadConsts* __restrict__ Q, float (&p)[kRows],
-                                       float* __restrict__ lp) {
+                                       const QuadConsts* __restrict__ Q, const float4* __restrict__ tab,
+                                       float (&p)[kRows], float* __restrict__ lp) {
   Far32 f;
   f.c1 = l.c1;
   f.c2 = l.c1 * lnq2;
@@ -264,14 +298,21 @@ __device__ __forceinline__ void line32(const Line32& l, int t_lo, int t_hi, int 
   // edge rows and rows near the core: per-lane masks, partial sums in LDS
   const unsigned core = zone_rows(l.J, zring, t_lo);
   const float S = l.C1 * (kSqrtPiF / l.y);
+  const bool ser = l.y < kSerYMax;
+  const int nt = series32_terms(l.y);
+  const float y_over_pi = l.y * (1.0f / kPiF);
   while (m) {
     const int rr = __builtin_ctz(m);
     m &= m - 1u;
     const float d = (float)(ib - 64 * rr) + l.phi;   // exact near the centre
     const float x = x_of_d32(d, f);
     float v;
-    if ((nearr >> rr) & 1u) v = S * ((core >> rr) & 1u ? core32(x, l.y, Q) : ring32(x, l.y, Q));
-    else v = lor ? far_value<true>(x, f) : far_value<false>(x, f);
+    if ((nearr >> rr) & 1u) {
+      if ((core >> rr) & 1u) v = S * (ser ? series32(x, l.y, y2, y_over_pi, nt, tab) : core32(x, l.y, Q));
+      else v = S * ring32(x, l.y, Q);
+    } else {
+      v = lor ? far_value<true>(x, f) : far_value<false>(x, f);
+    }
     const int j = t_lo + 64 * rr + lane;
     v = (j >= l.jlo && j <= l.jhi) ? v : 0.0f;
     lp[rr * 64 + lane] += v;
@@ -301,8 +342,14 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
                                                  int tiles_per_point, int total) {
   __shared__ float lds_p[kWavesPerWG][kWavePoints];   // partial sums of core/ring rows
   __shared__ float lds_c[kWavesPerWG][kWavePoints];   // Kahan compensations
+  __shared__ float4 lds_ser[kSerTerms * kSerIntervals]; // small-damping series table
   const int logical = tile_order(blockIdx.x, total);
   if (logical >= total) return;
+  {
+    const float4* __restrict__ src = reinterpret_cast<const float4*>(&Q->ser[0][0][0]);
+    for (int i = threadIdx.x; i < kSerTerms * kSerIntervals; i += blockDim.x) lds_ser[i] = src[i];
+    __syncthreads();
+  }
   const int pt = logical / tiles_per_point;
   const int tile = logical - pt * tiles_per_point;
   // wave index is uniform across the wave; say so, so that everything derived
@@ -344,7 +391,7 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);
       m &= m - 1;
-      line32(read_line32(cur, k), t_lo, t_hi, lane, lnq2, lnq6, q64, g64, Q, p, lp);
+      line32(read_line32(cur, k), t_lo, t_hi, lane, lnq2, lnq6, q64, g64, Q, lds_ser, p, lp);
       if (++since_flush == kFlushLines) {
         flush32(s, p, lp, lc, lane);
         since_flush = 0;

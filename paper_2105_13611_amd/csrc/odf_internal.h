@@ -45,6 +45,16 @@ constexpr int kTrap64Half = 12;                  // k = -12..12
 constexpr double kTrap64H = 0.5;
 constexpr double kTrap64Tmax = 6.0;
 
+// FP32 small-damping form for rows near the core of lines with a < 0.4:
+//   H(x, a) = e^{a^2 - x^2} cos(2 x a) + sum_k a^{2k+1} T_{2k+1}(x),
+//   T_n(x) = (-1)^{(n+1)/2} (2/sqrt(pi)) F^(n)(x) / n!,  F = Dawson's function,
+// the Taylor series in a of Re w(x + i a), with k < kSerTerms terms.  Each
+// T_n is tabulated against s = 1/(1 + x^2) in (0, 1] (all x) as one cubic per
+// interval of width 1/kSerIntervals.
+constexpr float kSerYMax = 0.4f;
+constexpr int kSerTerms = 4;
+constexpr int kSerIntervals = 128;
+
 // Half-width in fine points of the zone where |x| < R may occur, for a line
 // with c1 = ln q / b: |x| >= R implies |d| >= R / (1.02 c1) (|d ln q| <= 0.031).
 __host__ __device__ inline int32_t zone_half(double R, double c1) {
@@ -62,6 +72,8 @@ struct QuadConsts {
   double gh8_w[4];         // omega_k / pi
   double tr64_ci[2 * kTrap64Half + 1];
   double tr64_ch[2 * kTrap64Half + 1];
+  // T_{2k+1} on interval i: c0 + c1 f + c2 f^2 + c3 f^3, f = s kSerIntervals - i
+  alignas(16) float ser[kSerTerms][kSerIntervals][4];
 };
 
 // ---- resident line list (sorted by wavelength), structure of arrays --------

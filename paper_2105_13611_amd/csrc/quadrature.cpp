@@ -5,7 +5,8 @@
 // bisection in long double; weights are
 //   w_k = 2^{n-1} n! sqrt(pi) / (n^2 H_{n-1}(t_k)^2).
 // Trapezoidal-rule weights are (h/pi) e^{-t^2} at the nodes t = k h and
-// t = (k + 1/2) h, zero beyond the truncation |t| > tmax.
+// t = (k + 1/2) h, zero beyond the truncation |t| > tmax.  The small-damping
+// series table holds cubic pieces of the Dawson-derivative terms.
 #include <cmath>
 #include <vector>
 
@@ -65,6 +66,73 @@ void gauss_hermite_positive(int n, std::vector<long double>& t, std::vector<long
   }
 }
 
+// n-th derivative of Dawson's function F(x) = e^{-x^2} int_0^x e^{t^2} dt,
+// from Rybicki's sampling-theorem representation
+//   F(x) = lim_{h -> 0} pi^{-1/2} sum_{m odd} e^{-(x - m h)^2} / m
+// (G. B. Rybicki, Computers in Physics 3 (1989) 85).  With h = 0.2 the
+// representation error is of order e^{-(pi / 2h)^2} ~ 1e-27; each Gaussian is
+// differentiated exactly, d^n/dx^n e^{-u^2} = (-1)^n H_n(u) e^{-u^2}.  Unlike
+// the derivative recurrence F^(n+1) = -2x F^(n) - 2n F^(n-1), this keeps its
+// relative accuracy for x of order 10.
+long double dawson_derivative(int n, long double x) {
+  const long double h = 0.2L, L = 9.5L;
+  const long double inv_sqrt_pi = 0.564189583547756286948079451560772586L;
+  const long long m_lo = (long long)std::floor((x - L) / h) - 1;
+  const long long m_hi = (long long)std::ceil((x + L) / h) + 1;
+  long double sum = 0.0L;
+  for (long long m = m_lo; m <= m_hi; ++m) {
+    if ((m & 1LL) == 0) continue;
+    const long double u = x - (long double)m * h;
+    sum += hermite(n, u) * std::exp(-u * u) / (long double)m;
+  }
+  return ((n & 1) ? -sum : sum) * inv_sqrt_pi;
+}
+
+// (-1)^{(n+1)/2} (2/sqrt(pi)) / n!, so that T_n = coefficient * F^(n).
+long double series_coefficient(int n) {
+  const long double two_over_sqrt_pi = 1.128379167095512573896158903121545172L;
+  long double fact = 1.0L;
+  for (int k = 2; k <= n; ++k) fact *= k;
+  const long double sg = (((n + 1) / 2) & 1) ? -1.0L : 1.0L;
+  return sg * two_over_sqrt_pi / fact;
+}
+
+// Cubic Hermite pieces of T_n against s = 1/(1 + x^2).  dT/ds = T'(x) dx/ds
+// with dx/ds = -(1 + x^2)^2 / (2x); at s = 1 (x = 0, T even) dT/ds =
+// -T''(0)/2; at s = 0 (x -> infinity) T_1 ~ s / sqrt(pi) and T_n = O(s^2)
+// for n >= 3.
+void series_table(QuadConsts& Q) {
+  constexpr int NS = kSerIntervals;
+  const long double inv_sqrt_pi = 0.564189583547756286948079451560772586L;
+  for (int k = 0; k < kSerTerms; ++k) {
+    const int n = 2 * k + 1;
+    const long double c = series_coefficient(n);
+    std::vector<long double> v(NS + 1), d(NS + 1);
+    for (int i = 0; i <= NS; ++i) {
+      const long double s = (long double)i / NS;
+      if (i == 0) {
+        v[i] = 0.0L;
+        d[i] = (n == 1) ? inv_sqrt_pi : 0.0L;
+      } else if (i == NS) {
+        v[i] = c * dawson_derivative(n, 0.0L);
+        d[i] = -0.5L * c * dawson_derivative(n + 2, 0.0L);
+      } else {
+        const long double x = std::sqrt(1.0L / s - 1.0L);
+        v[i] = c * dawson_derivative(n, x);
+        d[i] = c * dawson_derivative(n + 1, x) * (-(1.0L + x * x) * (1.0L + x * x) / (2.0L * x));
+      }
+    }
+    const long double hs = 1.0L / NS;
+    for (int i = 0; i < NS; ++i) {
+      const long double v0 = v[i], v1 = v[i + 1], d0 = d[i] * hs, d1 = d[i + 1] * hs;
+      Q.ser[k][i][0] = (float)v0;
+      Q.ser[k][i][1] = (float)d0;
+      Q.ser[k][i][2] = (float)(3.0L * (v1 - v0) - 2.0L * d0 - d1);
+      Q.ser[k][i][3] = (float)(2.0L * (v0 - v1) + d0 + d1);
+    }
+  }
+}
+
 }  // namespace
 
 QuadConsts make_quad_consts() {
@@ -95,6 +163,7 @@ QuadConsts make_quad_consts() {
     Q.tr64_ci[k + kTrap64Half] = std::fabs(ti) <= tm ? (double)(h / pi * std::exp(-ti * ti)) : 0.0;
     Q.tr64_ch[k + kTrap64Half] = std::fabs(th) <= tm ? (double)(h / pi * std::exp(-th * th)) : 0.0;
   }
+  series_table(Q);
   return Q;
 }
 
