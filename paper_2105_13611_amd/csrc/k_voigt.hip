@@ -168,34 +168,13 @@ __device__ __forceinline__ float series32(float x, float y, float y2, float y_ov
   return fmaf(y, U, g);
 }
 
-// Line parameters broadcast to the wave (uniform values).
-struct Line32 {
-  int J, jlo, jhi, czh;
-  float phi, c1, C1, y;
-};
-
-__device__ __forceinline__ Line32 read_line32(const Rec32& r, int k) {
-  Line32 l;
-  l.J = __builtin_amdgcn_readlane(r.J, k);
-  l.jlo = __builtin_amdgcn_readlane(r.jlo, k);
-  l.jhi = __builtin_amdgcn_readlane(r.jhi, k);
-  l.czh = __builtin_amdgcn_readlane(r.czh, k);
-  l.phi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.phi), k));
-  l.c1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.c1), k));
-  l.C1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.C1), k));
-  l.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.y), k));
-  return l;
-}
-
-// Per-line constants of the far-wing evaluation.  With u = x^2 + y^2 + 1/2,
-// the two-node pair sum is S H = C1 u / (u^2 - 2 x^2), written in x^2 as
-//   (C1 x^2 + C1 C2) / (x^2 (x^2 + K1) + K2),  C2 = y^2 + 1/2,
-//   K1 = 2 y^2 - 1, K2 = C2^2;
-// in the Lorentz limit (y >= 1e4) S H = C1 / (x^2 + y^2).
+// Per-line constants of the evaluation in u = sigma x (the record's far-wing
+// fraction, with sigma folded into c1):
+//   u(d) = d (c1 + c2 d + c3 d^2), c2 = c1 ln q / 2, c3 = c1 (ln q)^2 / 6,
+//   u(row + 1) = u(row) q^-64 + step  (the frequency ratio of 64 points).
 struct Far32 {
-  float c1, c2, c3;   // x(d) = d (c1 + c2 d + c3 d^2)
-  float step;         // x(row + 1) = x(row) q^-64 + step
-  float A, B, K1, K2; // numerator A x^2 + B, denominator x^2 (x^2 + K1) + K2
+  float c1, c2, c3, step;
+  float A, B, K1, K2;
 };
 
 // Bit mask of the rows (of the wave's 16) that meet [J - half, J + half].
@@ -207,47 +186,43 @@ __device__ __forceinline__ unsigned zone_rows(int J, int half, int t_lo) {
   return ((2u << hi) - 1u) & ~((1u << lo) - 1u);
 }
 
-template <bool kLorentz>
-__device__ __forceinline__ float far_value(float x, const Far32& f) {
-  const float x2 = x * x;
-  if (kLorentz) return f.A * __builtin_amdgcn_rcpf(x2 + f.K2);
-  return fmaf(x2, f.A, f.B) * __builtin_amdgcn_rcpf(fmaf(x2, x2 + f.K1, f.K2));
+__device__ __forceinline__ float far_value(float u, const Far32& f) {
+  const float u2 = u * u;
+  return fmaf(u2, f.A, f.B) * __builtin_amdgcn_rcpf(fmaf(u2, u2 + f.K1, f.K2));
 }
 
 __device__ __forceinline__ float x_of_d32(float d, const Far32& f) {
   return d * fmaf(d, fmaf(d, f.c3, f.c2), f.c1);
 }
 
-// The window covers all 1024 points and no row is near the core: sixteen
-// rows in one block, no branches, no masks.  x is taken from the index
-// every fourth row and carried to the next row by the exact frequency
-// ratio q^-64 in between (one FMA).
-template <bool kLorentz>
-__device__ __forceinline__ void full_rows32(float d0, float q64, const Far32& f,
-                                            float (&p)[kRows]) {
+// Far rows wholly inside the window, given as a bit mask of the wave's 16
+// rows (all 16 when the window covers the tile and no row is near the core).
+// Rows go in groups of four: u is taken from the index at the start of a
+// group and carried to the next row by the exact frequency ratio q^-64 (one
+// FMA).  A row of a group that is not in the mask gets A = B = 0 (scalar
+// selects), so it adds an exact zero at no extra vector cost; groups with
+// no row in the mask are skipped.  This is the only place that updates the
+// register sums, so they stay in one set of registers.
+__device__ __forceinline__ void rows32(unsigned rows, float d0, float q64, const Far32& f,
+                                       float (&p)[kRows]) {
 #pragma unroll
   for (int g = 0; g < kRows; g += 4) {
-    float x = x_of_d32(d0 - (float)(64 * g), f);
+    const unsigned gm = (rows >> g) & 0xfu;
+    if (!gm) continue;
+    float u = x_of_d32(d0 - (float)(64 * g), f);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      p[g + r] += far_value<kLorentz>(x, f);
-      x = fmaf(x, q64, f.step);
+      const int on = -(int)((gm >> r) & 1u);   // all ones or zero (uniform)
+      const float A = __int_as_float(__float_as_int(f.A) & on);
+      const float B = __int_as_float(__float_as_int(f.B) & on);
+      const float u2 = u * u;
+      p[g + r] = fmaf(fmaf(u2, A, B), __builtin_amdgcn_rcpf(fmaf(u2, u2 + f.K1, f.K2)), p[g + r]);
+      u = fmaf(u, q64, f.step);
     }
   }
 }
 
-// Far rows wholly inside the window (bit mask), x from the index.
-template <bool kLorentz>
-__device__ __forceinline__ void inner_rows32(unsigned rows, float d0, const Far32& f,
-                                             float (&p)[kRows]) {
-#pragma unroll
-  for (int rr = 0; rr < kRows; ++rr) {
-    if (!((rows >> rr) & 1u)) continue;
-    p[rr] += far_value<kLorentz>(x_of_d32(d0 - (float)(64 * rr), f), f);
-  }
-}
-
-__device__ __forceinline__ void line32(const Line32& l, int t_lo, int t_hi, int lane, float lnq2,
+__device__ __forceinline__ void line32(const Rec32& l, int t_lo, int t_hi, int lane, float lnq2,
                                        float lnq6, float q64, float g64,
                                        const QuadConsts* __restrict__ Q, const float4* __restrict__ tab,
                                        float (&p)[kRows], float* __restrict__ lp) {
@@ -256,51 +231,39 @@ __device__ __forceinline__ void line32(const Line32& l, int t_lo, int t_hi, int 
   f.c2 = l.c1 * lnq2;
   f.c3 = l.c1 * lnq6;
   f.step = g64 * l.c1;
-  const bool lor = l.y >= 1.0e4f;   // Lorentz limit: pair correction below 1/(2 y^2)
-  const float y2 = l.y * l.y;
-  if (lor) {
-    f.A = l.C1;
-    f.B = 0.0f;
-    f.K1 = 0.0f;
-    f.K2 = y2;
-  } else {
-    const float C2 = y2 + Q->gh2_t2;
-    f.A = l.C1;
-    f.B = l.C1 * C2;
-    f.K1 = fmaf(2.0f, y2, -1.0f);
-    f.K2 = C2 * C2;
-  }
+  f.A = l.A;
+  f.B = l.B;
+  f.K1 = l.K1;
+  f.K2 = l.K2;
   const int ib = l.J - t_lo - lane;
   const float d0 = (float)ib + l.phi;
   const int zfar = (int)(short)(l.czh & 0xffff);   // |x| < 15 zone half-width
   const int zring = l.czh >> 16;                   // |x| < 6 zone half-width
   const unsigned near = zone_rows(l.J, zfar, t_lo);
-  if (!near && l.jlo <= t_lo && l.jhi >= t_lo + (kWavePoints - 1) &&
-      t_hi == t_lo + (kWavePoints - 1)) {
-    if (lor) full_rows32<true>(d0, q64, f, p);
-    else full_rows32<false>(d0, q64, f, p);
-    return;
-  }
   const int jl = max(l.jlo, t_lo) - t_lo;
   const int jh = min(l.jhi, t_hi) - t_lo;
   const int r_lo = jl >> 6, r_hi = jh >> 6;
   const unsigned rows = ((2u << r_hi) - 1u) & ~((1u << r_lo) - 1u);
-  // rows cut by the window edge (at most two)
+  // rows cut by the window edge (at most two); lanes past the grid's end are
+  // summed like the others and never stored
   unsigned edge = 0u;
   if (l.jlo > t_lo + 64 * r_lo) edge |= 1u << r_lo;
   if (l.jhi < t_lo + 64 * r_hi + 63) edge |= 1u << r_hi;
   const unsigned nearr = near & rows;
-  const unsigned inner = rows & ~nearr & ~edge;
-  if (lor) inner_rows32<true>(inner, d0, f, p);
-  else inner_rows32<false>(inner, d0, f, p);
+  // kept in a scalar register, so that the masks stay scalar operations
+  unsigned ne = near | edge;
+  asm("" : "+s"(ne));
+  rows32(rows & ~ne, d0, q64, f, p);
   unsigned m = (nearr | edge) & rows;
   if (!m) return;
   // edge rows and rows near the core: per-lane masks, partial sums in LDS
+  // (near rows exist only for a < 15, where sigma = 1 and u = x)
   const unsigned core = zone_rows(l.J, zring, t_lo);
-  const float S = l.C1 * (kSqrtPiF / l.y);
-  const bool ser = l.y < kSerYMax;
-  const int nt = series32_terms(l.y);
-  const float y_over_pi = l.y * (1.0f / kPiF);
+  const float y = l.y, S = l.S;
+  const float y2 = y * y;
+  const bool ser = y < kSerYMax;
+  const int nt = series32_terms(y);
+  const float y_over_pi = y * (1.0f / kPiF);
   while (m) {
     const int rr = __builtin_ctz(m);
     m &= m - 1u;
@@ -308,10 +271,10 @@ __device__ __forceinline__ void line32(const Line32& l, int t_lo, int t_hi, int 
     const float x = x_of_d32(d, f);
     float v;
     if ((nearr >> rr) & 1u) {
-      if ((core >> rr) & 1u) v = S * (ser ? series32(x, l.y, y2, y_over_pi, nt, tab) : core32(x, l.y, Q));
-      else v = S * ring32(x, l.y, Q);
+      if ((core >> rr) & 1u) v = S * (ser ? series32(x, y, y2, y_over_pi, nt, tab) : core32(x, y, Q));
+      else v = S * ring32(x, y, Q);
     } else {
-      v = lor ? far_value<true>(x, f) : far_value<false>(x, f);
+      v = far_value(x, f);
     }
     const int j = t_lo + 64 * rr + lane;
     v = (j >= l.jlo && j <= l.jhi) ? v : 0.0f;
@@ -380,18 +343,22 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
   const int c0 = lower_bound_J(rec, ns, t_lo - H);
   const int c1 = upper_bound_J(rec, ns, t_hi + H);
   int since_flush = 0;
-  // one record per lane, the next batch prefetched while this one is summed
-  Rec32 nxt{};
-  if (c0 + lane < c1) nxt = rec[c0 + lane];
+  // the windows of 64 records, one per lane, the next 64 prefetched while
+  // these are summed; each intersecting record is then read with scalar
+  // loads
+  // (lanes past the end hold an empty window that meets no tile)
+  const int2 none = make_int2(0x7fffffff, -0x7fffffff - 1);
+  int2 nxt = none;
+  if (c0 + lane < c1) nxt = *reinterpret_cast<const int2*>(&rec[c0 + lane].jlo);
   for (int base = c0; base < c1; base += 64) {
-    const Rec32 cur = nxt;
-    const bool valid = base + lane < c1;
-    if (base + 64 + lane < c1) nxt = rec[base + 64 + lane];
-    unsigned long long m = __ballot(valid && cur.jlo <= t_hi && cur.jhi >= t_lo);
+    const int2 cur = nxt;
+    nxt = none;
+    if (base + 64 + lane < c1) nxt = *reinterpret_cast<const int2*>(&rec[base + 64 + lane].jlo);
+    unsigned long long m = __ballot(cur.x <= t_hi && cur.y >= t_lo);
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);
       m &= m - 1;
-      line32(read_line32(cur, k), t_lo, t_hi, lane, lnq2, lnq6, q64, g64, Q, lds_ser, p, lp);
+      line32(rec[base + k], t_lo, t_hi, lane, lnq2, lnq6, q64, g64, Q, lds_ser, p, lp);
       if (++since_flush == kFlushLines) {
         flush32(s, p, lp, lc, lane);
         since_flush = 0;
