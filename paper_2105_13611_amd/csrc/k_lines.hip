@@ -359,9 +359,10 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
     const int32_t J = (int32_t)Jd;
     const int64_t slot = (int64_t)p * B.rec_stride + off;
     const double c1 = P.lnq / e.b;
-    int32_t czh;
+    int32_t czh, z40 = -1;
     if (kRec64) {
       czh = e.a < kFarR64 ? zone_half(kFarR64, c1) : -1;
+      z40 = e.a < kFar4R64 ? zone_half(kFar4R64, c1) : -1;
     } else {
       const int32_t far = e.a < kFarR32 ? zone_half(kFarR32, c1) : -1;
       const int32_t ring = e.a < kRingR32 ? zone_half(kRingR32, c1) : -1;
@@ -373,8 +374,9 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
       r.jlo = e.jlo;
       r.jhi = e.jhi;
       r.czh = czh;
+      r.z40 = z40;
       r.li = (int32_t)i;
-      r.pad0 = r.pad1 = r.pad2 = 0;
+      r.pad0 = r.pad1 = 0;
       r.phi = d.j0s - Jd;
       r.S = e.S;
       r.y = e.a;

@@ -376,7 +376,18 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
 
 // ---------------------------------------------------------------- FP64 ----
 
-// Eight-node Gauss-Hermite pair sum for |z| >= 10, one division.
+// 1/d for d > 0 in the normal range: the hardware approximation refined by
+// two Newton steps, e = 1 - d r, r <- r + r e (the error squares each step,
+// so the result is within about an ulp; no scaling or special cases needed).
+__device__ __forceinline__ double rcp64(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Eight-node Gauss-Hermite pair sum for |z| >= 10 (relative error < 5e-13).
 __device__ __forceinline__ double gh8(double x2, double y, double r2, const QuadConsts* __restrict__ Q) {
   const double p1 = r2 + Q->gh8_t2[0];
   const double d1 = fma(p1, p1, -4.0 * Q->gh8_t2[0] * x2);
@@ -388,11 +399,21 @@ __device__ __forceinline__ double gh8(double x2, double y, double r2, const Quad
     num = fma(num, dk, Q->gh8_w[k] * pk * den);
     den *= dk;
   }
-  return 2.0 * y * num / den;
+  return 2.0 * y * num * rcp64(den);
 }
 
-// Pole-corrected trapezoidal rule (FP64), any x reached by a core row.
-__device__ __forceinline__ double core64(double x, double y, const QuadConsts* __restrict__ Q) {
+// Four-node Gauss-Hermite pair sum for |z| >= 40 (relative error < 3e-12).
+__device__ __forceinline__ double gh4d(double x2, double y, double r2, const QuadConsts* __restrict__ Q) {
+  const double p1 = r2 + Q->gh4_t2d[0], p2 = r2 + Q->gh4_t2d[1];
+  const double d1 = fma(p1, p1, -4.0 * Q->gh4_t2d[0] * x2);
+  const double d2 = fma(p2, p2, -4.0 * Q->gh4_t2d[1] * x2);
+  const double num = fma(Q->gh4_wd[0] * p1, d2, Q->gh4_wd[1] * p2 * d1);
+  return 2.0 * y * num * rcp64(d1 * d2);
+}
+
+// Pole-corrected trapezoidal rule (FP64), any x reached by a core row; ep is
+// the line's e^{-2 pi a / h}.
+__device__ __forceinline__ double core64(double x, double y, double ep, const QuadConsts* __restrict__ Q) {
   constexpr double h = kTrap64H;
   constexpr double invh = 1.0 / kTrap64H;
   const double y2 = y * y;
@@ -410,17 +431,16 @@ __device__ __forceinline__ double core64(double x, double y, const QuadConsts* _
     num = fma(num, D, ck * den);
     den *= D;
   }
-  double v = y * num / den;
+  double v = y * num * rcp64(den);
   if (y < kPi * invh) {
     const double e2 = 2.0 * kPi * y * invh;
     const double mag = exp(y2 - x * x - e2);
-    const double ep = exp(-e2);
     double sph, cph, sth, cth;
     sincospi(2.0 * hx, &sph, &cph);
     sincospi(2.0 * hx - 2.0 * x * y / kPi, &sth, &cth);
     const double sgn = sh ? 1.0 : -1.0;
     const double dre = fma(ep, cph, sgn), dim = ep * sph;
-    v += 2.0 * mag * (cth * dre + sth * dim) / fma(dre, dre, dim * dim);
+    v += 2.0 * mag * (cth * dre + sth * dim) * rcp64(fma(dre, dre, dim * dim));
   }
   return v;
 }
@@ -440,32 +460,7 @@ __device__ __forceinline__ double x_of_d64(double d, double c1, double lnq) {
   return d * c1 * e;
 }
 
-struct Line64 {
-  int J, jlo, jhi, czh;
-  double phi, S, y, c1;
-};
-
-__device__ __forceinline__ double readlane_f64(double v, int k) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-__device__ __forceinline__ Line64 read_line64(const Rec64& r, int k) {
-  Line64 l;
-  l.J = __builtin_amdgcn_readlane(r.J, k);
-  l.jlo = __builtin_amdgcn_readlane(r.jlo, k);
-  l.jhi = __builtin_amdgcn_readlane(r.jhi, k);
-  l.czh = __builtin_amdgcn_readlane(r.czh, k);
-  l.phi = readlane_f64(r.phi, k);
-  l.S = readlane_f64(r.S, k);
-  l.y = readlane_f64(r.y, k);
-  l.c1 = readlane_f64(r.c1, k);
-  return l;
-}
-
-__device__ __forceinline__ void line64(const Line64& l, int t_lo, int t_hi, int lane, double lnq,
+__device__ __forceinline__ void line64(const Rec64& l, int t_lo, int t_hi, int lane, double lnq,
                                        double q64, double g64, const QuadConsts* __restrict__ Q,
                                        double (&as)[kRows], double* __restrict__ ls) {
   const double y2 = l.y * l.y;
@@ -475,6 +470,7 @@ __device__ __forceinline__ void line64(const Line64& l, int t_lo, int t_hi, int 
   const int r_lo = jl >> 6, r_hi = jh >> 6;
   const unsigned rows = ((2u << r_hi) - 1u) & ~((1u << r_lo) - 1u);
   const unsigned core = zone_rows(l.J, l.czh, t_lo) & rows;
+  const unsigned mid = zone_rows(l.J, l.z40, t_lo) & rows & ~core;
   const unsigned far = rows & ~core;
   // x from the index at the first row of each run of rows, then carried to
   // the next row by the exact frequency ratio q^-64 (one FMA)
@@ -486,7 +482,7 @@ __device__ __forceinline__ void line64(const Line64& l, int t_lo, int t_hi, int 
     if (rr == 0 || !((far >> (rr - 1)) & 1u)) x = x_of_d64((double)(ib - 64 * rr) + l.phi, l.c1, lnq);
     else x = fma(x, q64, step);
     const double x2 = x * x;
-    double v = l.S * gh8(x2, l.y, x2 + y2, Q);
+    double v = l.S * ((mid >> rr) & 1u ? gh8(x2, l.y, x2 + y2, Q) : gh4d(x2, l.y, x2 + y2, Q));
     const int rs = t_lo + 64 * rr;
     if (rs < l.jlo || rs + 63 > l.jhi) {
       const int j = rs + lane;
@@ -495,12 +491,14 @@ __device__ __forceinline__ void line64(const Line64& l, int t_lo, int t_hi, int 
     as[rr] += v;
   }
   unsigned m = core;
+  if (!m) return;
+  const double ep = exp(-2.0 * kPi * l.y / kTrap64H);
   while (m) {
     const int rr = __builtin_ctz(m);
     m &= m - 1u;
     const double d = (double)(ib - 64 * rr) + l.phi;
     const double x = x_of_d64(d, l.c1, lnq);
-    double v = l.S * core64(x, l.y, Q);
+    double v = l.S * core64(x, l.y, ep, Q);
     const int j = t_lo + 64 * rr + lane;
     v = (j >= l.jlo && j <= l.jhi) ? v : 0.0;
     ls[rr * 64 + lane] += v;
@@ -536,17 +534,19 @@ __global__ __launch_bounds__(256) void k_voigt64(Params P, Batch B, const QuadCo
   const double g64 = expm1(-64.0 * lnq) / lnq;      // (q^-64 - 1) / ln q
   const int c0 = lower_bound_J(rec, ns, t_lo - H);
   const int c1 = upper_bound_J(rec, ns, t_hi + H);
-  Rec64 nxt{};
-  if (c0 + lane < c1) nxt = rec[c0 + lane];
+  // windows one per lane (next 64 prefetched), records by scalar loads
+  const int2 none = make_int2(0x7fffffff, -0x7fffffff - 1);
+  int2 nxt = none;
+  if (c0 + lane < c1) nxt = *reinterpret_cast<const int2*>(&rec[c0 + lane].jlo);
   for (int base = c0; base < c1; base += 64) {
-    const Rec64 cur = nxt;
-    const bool valid = base + lane < c1;
-    if (base + 64 + lane < c1) nxt = rec[base + 64 + lane];
-    unsigned long long m = __ballot(valid && cur.jlo <= t_hi && cur.jhi >= t_lo);
+    const int2 cur = nxt;
+    nxt = none;
+    if (base + 64 + lane < c1) nxt = *reinterpret_cast<const int2*>(&rec[base + 64 + lane].jlo);
+    unsigned long long m = __ballot(cur.x <= t_hi && cur.y >= t_lo);
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);
       m &= m - 1;
-      line64(read_line64(cur, k), t_lo, t_hi, lane, lnq, q64, g64, Q, as, ls);
+      line64(rec[base + k], t_lo, t_hi, lane, lnq, q64, g64, Q, as, ls);
     }
   }
   double* kap = reinterpret_cast<double*>(B.kappa) + p * B.kappa_stride;

@@ -38,9 +38,11 @@ constexpr float kRingR32 = 6.0f;
 constexpr int kTrap32Half = 6;                   // k = -6..6
 constexpr float kTrap32H = 0.75f;
 constexpr float kTrap32Tmax = 4.2f;
-// FP64: rows with all |x| >= 10 -> eight-node Gauss-Hermite pair sum; other
-// rows -> trapezoid h = 0.5, nodes |t| <= 6, for every lane.
+// FP64: rows with all |x| >= 40 -> four-node Gauss-Hermite pair sum (relative
+// error below 3e-12); all |x| >= 10 -> eight-node (below 5e-13); other rows ->
+// trapezoid h = 0.5, nodes |t| <= 6, for every lane.
 constexpr double kFarR64 = 10.0;
+constexpr double kFar4R64 = 40.0;
 constexpr int kTrap64Half = 12;                  // k = -12..12
 constexpr double kTrap64H = 0.5;
 constexpr double kTrap64Tmax = 6.0;
@@ -70,6 +72,8 @@ struct QuadConsts {
   float tr32_ch[2 * kTrap32Half + 1];   // (h/pi) e^{-t^2}, t = (k + 1/2) h
   double gh8_t2[4];        // t_k^2 of the 8-node rule
   double gh8_w[4];         // omega_k / pi
+  double gh4_t2d[2];       // t_k^2 of the 4-node rule (FP64)
+  double gh4_wd[2];        // omega_k / pi
   double tr64_ci[2 * kTrap64Half + 1];
   double tr64_ch[2 * kTrap64Half + 1];
   // T_{2k+1} on interval i: c0 + c1 f + c2 f^2 + c3 f^3, f = s kSerIntervals - i
@@ -124,8 +128,11 @@ struct alignas(16) Rec32 {
   float y;          // damping parameter a
 };
 struct alignas(16) Rec64 {
-  int32_t J, jlo, jhi, czh;
-  int32_t li, pad0, pad1, pad2;   // sorted line index (stage checks)
+  int32_t J, jlo, jhi;
+  int32_t czh;      // half-width of the zone where |x| < 10 may occur (-1: none)
+  int32_t z40;      // the same for |x| < 40
+  int32_t li;       // sorted line index (stage checks)
+  int32_t pad0, pad1;
   double phi, S, y, c1;
 };
 

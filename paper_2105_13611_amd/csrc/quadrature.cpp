@@ -145,6 +145,8 @@ QuadConsts make_quad_consts() {
   for (int k = 0; k < 2; ++k) {
     Q.gh4_t2[k] = (float)(t[k] * t[k]);
     Q.gh4_w[k] = (float)(w[k] / pi);
+    Q.gh4_t2d[k] = (double)(t[k] * t[k]);
+    Q.gh4_wd[k] = (double)(w[k] / pi);
   }
   gauss_hermite_positive(8, t, w);
   for (int k = 0; k < 4; ++k) {
