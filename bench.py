@@ -10,7 +10,10 @@ compensated ("mixed") path is the headline value, the plain FP64 path is
 reported beside it.
 
 Roofline of the dominant kernel (the Voigt scatter-sum) is measured live with
-HIP events the library records around every launch on the compute stream.
+HIP events the library records around every launch on its stream; the rate
+uses the union of the launch intervals (the two internal streams overlap
+launches), and the HBM traffic comes from the committed counter summary
+while the kernel sources still match it.
 The CPU baseline times the FP64 oracle on a bounded stratified sample of the
 same workload and scales it to points/s.
 
@@ -29,12 +32,14 @@ sys.path.insert(0, ROOT)
 METRIC = "ODF (T,P) points/s + line evals/s, FP32 vs FP64 plain at ≤1e-3 ODF err"
 
 # nominal FP32 operations per Voigt sample on the far-wing path (the path
-# almost every sample takes), FMA = 2: x from the index 5, x^2 1, numerator
-# 2, denominator 3, reciprocal 1, product 1, compensated add 4
-FLOP_PER_SAMPLE_F32 = 17
-# FP64 path: x(d) 16, x^2 1, r 1, four GH pairs 4*(1+3)+3*3, division 1,
-# scale 3, accumulate 1
-FLOP_PER_SAMPLE_F64 = 48
+# almost every sample takes), FMA = 2: u carried from the previous row 2,
+# u from the index every fourth row 5/4, u^2 1, numerator 2, denominator 3,
+# reciprocal 1, accumulate 2, compensated add every 16 lines 4/16
+FLOP_PER_SAMPLE_F32 = 12.5
+# FP64 far wing (four-node pair): x carried 2, x^2 1, r^2 1, two pairs
+# 2*(1+1+2), numerator 5, product 1, reciprocal with two Newton steps 9,
+# scale 4, accumulate 1
+FLOP_PER_SAMPLE_F64 = 32
 # VALU peak without packed FP32 (disabled in this build): 256 CU x 4 SIMD x
 # 16 lanes x 2 FLOP per FMA x 2.4 GHz
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -91,17 +96,49 @@ def run_gpu(w, precision, steps, warmup, workspace_gb, points_idx=None, batch_po
     return res
 
 
-def roofline(res, flop_per_sample):
-    ms, launches = res["stage_ms"]["voigt"]
-    samples = res["stats"]["voigt_samples"] * res["steps"]
-    if launches == 0 or ms <= 0:
+def kernel_sources_sha256():
+    """Hash of the sources that define the Voigt kernels: a traffic figure
+    taken from counters applies only while it matches."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_voigt.hip", "odf_internal.h"):
+        with open(os.path.join(ROOT, "paper_2105_13611_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(precision):
+    """HBM bytes per Voigt launch from the committed counter summary of the
+    full-table run (FETCH_SIZE + WRITE_SIZE, each scaled by its copy-kernel
+    calibration), or None when there is none or the kernel has changed."""
+    path = os.path.join(ROOT, "profiles", f"voigt{32 if precision == 'mixed' else 64}_full_table_hbm_traffic.md")
+    if not os.path.exists(path):
         return None
-    avg_s = ms / 1e3 / launches
+    txt = open(path).read()
+    i = txt.find("```json")
+    if i < 0:
+        return None
+    d = json.loads(txt[i + 7: txt.index("```", i + 7)])
+    if d.get("source_sha256") != kernel_sources_sha256():
+        return None
+    return d["hbm_bytes_per_launch"]
+
+
+def roofline(res, flop_per_sample, precision):
+    st = res["stage_ms"]["voigt"]
+    ms, busy, launches = st["ms"], st["busy_ms"], st["launches"]
+    samples = res["stats"]["voigt_samples"] * res["steps"]
+    if launches == 0 or busy <= 0:
+        return None
+    # launches of the two internal streams overlap: a launch's own duration
+    # counts time it shares the GPU with the other stream, so the rate is
+    # taken over the union of the kernel's launch intervals
     flop_per_launch = samples * flop_per_sample / launches
-    achieved = flop_per_launch / avg_s / 1e12
+    achieved = flop_per_launch / (busy / 1e3 / launches) / 1e12
     return dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
-                frac=achieved / PEAK_VALU_TFLOPS, traffic=None, kernel="voigt scatter-sum",
-                avg_launch_ms=ms / launches, launches=launches,
+                frac=achieved / PEAK_VALU_TFLOPS, traffic=traffic_per_launch(precision),
+                kernel="voigt scatter-sum", avg_launch_ms=ms / launches,
+                busy_ms_per_launch=busy / launches, launches=launches,
                 samples_per_launch=samples / launches, flop_per_sample=flop_per_sample)
 
 
@@ -226,6 +263,8 @@ def main():
     ap.add_argument("--batch-points", type=int, default=0, help="points per device batch (0 = automatic)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first copy a buffer of this size three times (a reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -233,6 +272,15 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb << 18   # float32 elements
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)   # an elementwise kernel (a same-type copy_ may use DMA)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {args.copy_calibration_mb} MiB")
+        del a, b
     if args.mode == "serve":
         print(json.dumps(run_serving(args.serve_requests, args.serve_rate, args.workspace_gb,
                                      args.serve_max_points)), flush=True)
@@ -255,7 +303,7 @@ def main():
     n_pts = head["n_points"]
     value = n_pts * head["steps"] / head["seconds"]
     line_evals = head["stats"]["line_evals"] * head["steps"] / head["seconds"]
-    rl = roofline(head, FLOP_PER_SAMPLE_F32 if precs[0] == "mixed" else FLOP_PER_SAMPLE_F64)
+    rl = roofline(head, FLOP_PER_SAMPLE_F32 if precs[0] == "mixed" else FLOP_PER_SAMPLE_F64, precs[0])
     if rl:
         rl["frac_of_datasheet_fp32"] = rl["achieved"] / (PEAK_F32_DATASHEET if precs[0] == "mixed" else PEAK_F64_DATASHEET)
     out = {
@@ -279,11 +327,12 @@ def main():
         r = res[p]
         out[f"{p}_path"] = dict(points_per_s=r["n_points"] * r["steps"] / r["seconds"],
                                 seconds_per_step=r["seconds"] / r["steps"],
-                                stage_ms={k: v[0] for k, v in r["stage_ms"].items()},
+                                stage_ms={k: v["ms"] for k, v in r["stage_ms"].items()},
+                                stage_busy_ms={k: v["busy_ms"] for k, v in r["stage_ms"].items()},
                                 plan_seconds=r["plan_seconds"], checksum=r["checksum"])
     if "fp64" in res and "mixed" in res:
         out["mixed_over_fp64_speedup"] = out["mixed_path"]["points_per_s"] / out["fp64_path"]["points_per_s"]
-        out["roofline_fp64"] = roofline(res["fp64"], FLOP_PER_SAMPLE_F64)
+        out["roofline_fp64"] = roofline(res["fp64"], FLOP_PER_SAMPLE_F64, "fp64")
     if not args.no_cpu:
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
         log(f"[bench] CPU baseline: oracle on {workers} processes")

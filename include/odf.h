@@ -228,10 +228,15 @@ odf_status odf_stage_reduce(odf_plan_t *plan, const void *kappa_dev, void *out_d
 
 /* Kernel times accumulated by odf_compute when options.kernel_timing is set,
  * per stage: 0 point state, 1 line selection, 2 survivor scan, 3 survivor
- * emission, 4 Voigt scatter-sum, 5 ODF reduction.  ms[6] receives the summed
- * HIP-event durations in milliseconds, launches[6] the launch counts; reset
- * nonzero clears the totals afterwards. */
-odf_status odf_stage_times(odf_plan_t *plan, double *ms, int64_t *launches, int32_t reset);
+ * emission, 4 Voigt scatter-sum, 5 ODF reduction.  All arrays are host
+ * [6], caller-owned.  ms receives the summed HIP-event durations of the
+ * launches in milliseconds; busy_ms the length of the union of their
+ * intervals (less than ms when odf_compute's two internal streams run
+ * launches of one stage at the same time); launches the launch counts.
+ * reset nonzero clears the totals afterwards.  ODF_E_INVALID for a NULL
+ * argument. */
+odf_status odf_stage_times(odf_plan_t *plan, double *ms, double *busy_ms, int64_t *launches,
+                           int32_t reset);
 
 /* Test hook for failure handling: the next batch of `ticket` that the
  * request loop launches reports a launch error instead of running, so the

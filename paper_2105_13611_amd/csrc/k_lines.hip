@@ -358,6 +358,7 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
     const double Jd = rint(d.j0s);
     const int32_t J = (int32_t)Jd;
     const int64_t slot = (int64_t)p * B.rec_stride + off;
+    B.win[slot] = make_int2(e.jlo, e.jhi);
     const double c1 = P.lnq / e.b;
     int32_t czh, z40 = -1;
     if (kRec64) {

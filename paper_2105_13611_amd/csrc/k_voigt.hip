@@ -46,8 +46,10 @@ constexpr int kMinWaves32 = 1;
 // every XCD gets an equal share of every point.  (Giving each XCD a
 // contiguous range of points instead would let one expensive point -- costs
 // differ by two orders of magnitude across the T-P grid -- idle the other
-// XCDs; the survivors a tile reads are a few MB per point, so L2 sharing
-// between neighbouring tiles is not worth that imbalance.)
+// XCDs.  Runs of 8 neighbouring tiles per XCD, for L2 sharing of the
+// records they read, measured no change in time or in HBM reads: the
+// records that concurrently resident workgroups stream exceed the L2 either
+// way.)
 __device__ __forceinline__ int tile_order(int bid, int total) {
   (void)total;
   return bid;
@@ -334,6 +336,7 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
     p[rr] = 0.0f;
   }
   const Rec32* __restrict__ rec = reinterpret_cast<const Rec32*>(B.rec) + pt * B.rec_stride;
+  const int2* __restrict__ win = B.win + pt * B.rec_stride;
   const int ns = B.nsurv[pt];
   const int H = B.hmax[pt];
   const float lnq = (float)P.lnq;
@@ -343,17 +346,17 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
   const int c0 = lower_bound_J(rec, ns, t_lo - H);
   const int c1 = upper_bound_J(rec, ns, t_hi + H);
   int since_flush = 0;
-  // the windows of 64 records, one per lane, the next 64 prefetched while
-  // these are summed; each intersecting record is then read with scalar
-  // loads
+  // the windows of 64 records (from the compact window array), one per
+  // lane, the next 64 prefetched while these are summed; each intersecting
+  // record is then read with scalar loads
   // (lanes past the end hold an empty window that meets no tile)
   const int2 none = make_int2(0x7fffffff, -0x7fffffff - 1);
   int2 nxt = none;
-  if (c0 + lane < c1) nxt = *reinterpret_cast<const int2*>(&rec[c0 + lane].jlo);
+  if (c0 + lane < c1) nxt = win[c0 + lane];
   for (int base = c0; base < c1; base += 64) {
     const int2 cur = nxt;
     nxt = none;
-    if (base + 64 + lane < c1) nxt = *reinterpret_cast<const int2*>(&rec[base + 64 + lane].jlo);
+    if (base + 64 + lane < c1) nxt = win[base + 64 + lane];
     unsigned long long m = __ballot(cur.x <= t_hi && cur.y >= t_lo);
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);
@@ -527,6 +530,7 @@ __global__ __launch_bounds__(256) void k_voigt64(Params P, Batch B, const QuadCo
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) as[rr] = 0.0;
   const Rec64* __restrict__ rec = reinterpret_cast<const Rec64*>(B.rec) + p * B.rec_stride;
+  const int2* __restrict__ win = B.win + p * B.rec_stride;
   const int ns = B.nsurv[p];
   const int H = B.hmax[p];
   const double lnq = P.lnq;
@@ -537,11 +541,11 @@ __global__ __launch_bounds__(256) void k_voigt64(Params P, Batch B, const QuadCo
   // windows one per lane (next 64 prefetched), records by scalar loads
   const int2 none = make_int2(0x7fffffff, -0x7fffffff - 1);
   int2 nxt = none;
-  if (c0 + lane < c1) nxt = *reinterpret_cast<const int2*>(&rec[c0 + lane].jlo);
+  if (c0 + lane < c1) nxt = win[c0 + lane];
   for (int base = c0; base < c1; base += 64) {
     const int2 cur = nxt;
     nxt = none;
-    if (base + 64 + lane < c1) nxt = *reinterpret_cast<const int2*>(&rec[base + 64 + lane].jlo);
+    if (base + 64 + lane < c1) nxt = win[base + 64 + lane];
     unsigned long long m = __ballot(cur.x <= t_hi && cur.y >= t_lo);
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);

@@ -152,6 +152,7 @@ struct Batch {
   int32_t* hmax;        // [B]         max half-window in fine points
   unsigned long long* nsamp;  // [B]
   void* rec;            // [B][L] Rec32 or Rec64
+  int2* win;            // [B][L] (jlo, jhi) of each record, scanned by the Voigt kernels
   void* kappa;          // [B][N] float or double
   int64_t rec_stride;   // = L
   int64_t kappa_stride; // = N

@@ -197,6 +197,7 @@ SlotLayout make_slot(const odf_plan_s* p, int32_t pts) {
   s.off_hmax = take(4 * pts);
   s.off_nsamp = take(8 * pts);
   s.off_rec = take((mixed ? (int64_t)sizeof(Rec32) : (int64_t)sizeof(Rec64)) * std::max<int64_t>(L, 1) * pts);
+  s.off_win = take((int64_t)sizeof(int2) * std::max<int64_t>(L, 1) * pts);
   s.off_kappa = take((mixed ? 4 : 8) * p->N * pts);
   s.off_gscr = take((mixed ? 4 : 8) * std::max<int64_t>(p->gscr_elems, 1) * pts);
   s.bytes = o;
@@ -220,6 +221,7 @@ Batch make_batch(const odf_plan_s* p, const SlotLayout& s, char* base, int32_t n
   B.hmax = reinterpret_cast<int32_t*>(base + s.off_hmax);
   B.nsamp = reinterpret_cast<unsigned long long*>(base + s.off_nsamp);
   B.rec = base + s.off_rec;
+  B.win = reinterpret_cast<int2*>(base + s.off_win);
   B.kappa = base + s.off_kappa;
   B.rec_stride = std::max<int64_t>(p->n_lines, 1);
   B.kappa_stride = p->N;
@@ -270,14 +272,38 @@ odf_status enqueue_batch(odf_plan_s* p, const Batch& B, char* slot_base, const S
   return ODF_OK;
 }
 
-// After the stream has drained: add the recorded pairs to the totals.
+// After the streams have drained: add the recorded pairs to the totals.
+// Launches on different streams may overlap, so besides the summed
+// durations each stage gets the length of the union of its launch intervals
+// (times taken relative to the first recorded event).
 void collect_timer(StageTimer& t) {
+  std::vector<std::pair<float, float>> iv[kStages];
   for (size_t i = 0; i < t.used; ++i) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, t.pool[2 * i], t.pool[2 * i + 1]) == hipSuccess) {
-      t.ms[t.stage_of_pair[i]] += ms;
-      t.launches[t.stage_of_pair[i]] += 1;
+    float ms = 0.0f, t0 = 0.0f, t1 = 0.0f;
+    if (hipEventElapsedTime(&ms, t.pool[2 * i], t.pool[2 * i + 1]) != hipSuccess) continue;
+    const int k = t.stage_of_pair[i];
+    t.ms[k] += ms;
+    t.launches[k] += 1;
+    if (hipEventElapsedTime(&t0, t.pool[0], t.pool[2 * i]) == hipSuccess &&
+        hipEventElapsedTime(&t1, t.pool[0], t.pool[2 * i + 1]) == hipSuccess)
+      iv[k].emplace_back(t0, t1);
+  }
+  for (int k = 0; k < kStages; ++k) {
+    std::sort(iv[k].begin(), iv[k].end());
+    double total = 0.0, a = 0.0, b = 0.0;
+    bool open = false;
+    for (const auto& x : iv[k]) {
+      if (open && x.first <= b) {
+        b = std::max(b, (double)x.second);
+        continue;
+      }
+      if (open) total += b - a;
+      a = x.first;
+      b = x.second;
+      open = true;
     }
+    if (open) total += b - a;
+    t.busy_ms[k] += total;
   }
   t.used = 0;
 }
@@ -565,15 +591,18 @@ odf_status odf_plan(const odf_lines* lines, const odf_species* species, const od
 
 int64_t odf_point_footprint(const odf_plan_t* plan) { return plan ? plan->per_point_bytes : -1; }
 
-odf_status odf_stage_times(odf_plan_t* plan, double* ms, int64_t* launches, int32_t reset) {
+odf_status odf_stage_times(odf_plan_t* plan, double* ms, double* busy_ms, int64_t* launches,
+                           int32_t reset) {
   g_err.clear();
-  if (!plan || !ms || !launches) { set_error("odf_stage_times: NULL argument"); return ODF_E_INVALID; }
+  if (!plan || !ms || !busy_ms || !launches) { set_error("odf_stage_times: NULL argument"); return ODF_E_INVALID; }
   std::lock_guard<std::mutex> guard(plan->compute_mu);
   for (int k = 0; k < kStages; ++k) {
     ms[k] = plan->timer.ms[k];
+    busy_ms[k] = plan->timer.busy_ms[k];
     launches[k] = plan->timer.launches[k];
     if (reset) {
       plan->timer.ms[k] = 0.0;
+      plan->timer.busy_ms[k] = 0.0;
       plan->timer.launches[k] = 0;
     }
   }

@@ -25,7 +25,7 @@ void g_last_error_clear();
 // Layout of one batch slot inside the workspace.
 struct SlotLayout {
   int64_t off_T, off_logP, off_vt, off_abund, off_state, off_pop, off_bT, off_flags, off_blk,
-      off_nsurv, off_hmax, off_nsamp, off_rec, off_kappa, off_gscr;
+      off_nsurv, off_hmax, off_nsamp, off_rec, off_win, off_kappa, off_gscr;
   int64_t bytes;      // total bytes of the slot
   int32_t points;     // points per slot
 };
@@ -36,7 +36,8 @@ struct StageTimer {
   std::vector<hipEvent_t> pool;      // event pairs, reused between calls
   std::vector<int> stage_of_pair;    // stage of each recorded pair
   size_t used = 0;                   // pairs recorded since the last collect
-  double ms[kStages] = {0, 0, 0, 0, 0, 0};
+  double ms[kStages] = {0, 0, 0, 0, 0, 0};       // summed launch durations
+  double busy_ms[kStages] = {0, 0, 0, 0, 0, 0};  // union of the launch intervals
   int64_t launches[kStages] = {0, 0, 0, 0, 0, 0};
 };
 

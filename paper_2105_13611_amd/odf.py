@@ -89,7 +89,7 @@ SIGNATURES = {
     "odf_stage_fine": (C.c_int, [C.c_void_p, C.POINTER(OdfRequest), C.c_int32, C.c_void_p]),
     "odf_stage_reduce": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "odf_debug_fail_next_batch": (C.c_int, [C.c_void_p, C.c_int64]),
-    "odf_stage_times": (C.c_int, [C.c_void_p, _D, _I64, C.c_int32]),
+    "odf_stage_times": (C.c_int, [C.c_void_p, _D, _D, _I64, C.c_int32]),
 }
 
 
@@ -294,11 +294,16 @@ class Plan:
     STAGES = ("point_state", "select", "scan", "emit", "voigt", "odf")
 
     def stage_times(self, reset=True):
-        """{stage: (total ms, launches)} from the HIP events of odf_compute."""
+        """{stage: {"ms", "busy_ms", "launches"}} from the HIP events of
+        odf_compute: summed launch durations, the union of the launch
+        intervals, and the launch count."""
         ms = np.zeros(6)
+        busy = np.zeros(6)
         n = np.zeros(6, np.int64)
-        _check(lib().odf_stage_times(self.handle, _ptr(ms, _D), _ptr(n, _I64), int(bool(reset))))
-        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.STAGES)}
+        _check(lib().odf_stage_times(self.handle, _ptr(ms, _D), _ptr(busy, _D), _ptr(n, _I64),
+                                     int(bool(reset))))
+        return {k: dict(ms=float(ms[i]), busy_ms=float(busy[i]), launches=int(n[i]))
+                for i, k in enumerate(self.STAGES)}
 
     def fail_next_batch(self, ticket):
         _check(lib().odf_debug_fail_next_batch(self.handle, int(ticket)))

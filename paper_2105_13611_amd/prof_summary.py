@@ -1,0 +1,119 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+  python -m paper_2105_13611_amd.prof_summary stats --csv <run_kernel_stats.csv>
+      --command "<profiled command>" --title "..." --out profiles/<name>.md
+  python -m paper_2105_13611_amd.prof_summary traffic --fetch <counter csv>
+      --write <counter csv> --copy-mb 1024 --kernel k_voigt32
+      --command "<profiled command>" --out profiles/<name>.md
+
+`traffic` scales each kernel's FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+by the ratio of the bytes a plain elementwise copy of known size moves to what
+the same counter reads for it, and records the hash of the Voigt kernel
+sources, so that the benchmark can tell whether the figure still applies.
+"""
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in ("k_voigt.hip", "odf_internal.h"):
+        with open(os.path.join(ROOT, "paper_2105_13611_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def short_name(name):
+    m = re.search(r"(k_\w+|\w*elementwise\w*|\w*copy\w*)", name)
+    return m.group(1) if m else name[:60]
+
+
+def stats(args):
+    rows = list(csv.DictReader(open(args.csv)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# {args.title}", "", "Command (run from the repository root on one MI355X):", "",
+             "```", args.command, "```", "",
+             "| kernel | calls | total ms | avg ms | min ms | max ms | % |", "|---|---|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"| {short_name(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.1f} | "
+                     f"{float(r['AverageNs']) / 1e6:.3f} | {float(r['MinNs']) / 1e6:.3f} | "
+                     f"{float(r['MaxNs']) / 1e6:.3f} | {100 * float(r['TotalDurationNs']) / total:.1f} |")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
+def per_dispatch(path, counter):
+    """{dispatch id: (kernel name, value)} for one counter."""
+    out = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        d = int(r["Dispatch_Id"])
+        name, v = out.get(d, (r["Kernel_Name"], 0.0))
+        out[d] = (name, v + float(r["Counter_Value"]))
+    return out
+
+
+def traffic(args):
+    copy_bytes = args.copy_mb << 20
+    res = {}
+    for counter, path in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+        d = per_dispatch(path, counter)
+        copies = [v for n, v in d.values() if "elementwise" in n or "mul" in short_name(n)]
+        # the calibration copies are the largest elementwise dispatches
+        copies = sorted(copies)[-3:]
+        kib = sum(copies) / len(copies)
+        factor = copy_bytes / (kib * 1024.0)
+        ker = [v for n, v in d.values() if args.kernel in n]
+        res[counter] = dict(copy_kib=kib, factor=factor, dispatches=len(ker),
+                            bytes_per_launch=factor * 1024.0 * sum(ker) / len(ker))
+    hbm = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    summary = dict(kernel=args.kernel, source_sha256=kernel_sources_sha256(),
+                   hbm_bytes_per_launch=hbm,
+                   fetch_bytes_per_launch=res["FETCH_SIZE"]["bytes_per_launch"],
+                   write_bytes_per_launch=res["WRITE_SIZE"]["bytes_per_launch"],
+                   launches=res["FETCH_SIZE"]["dispatches"],
+                   copy_bytes=copy_bytes, fetch_factor=res["FETCH_SIZE"]["factor"],
+                   write_factor=res["WRITE_SIZE"]["factor"],
+                   copy_fetch_kib=res["FETCH_SIZE"]["copy_kib"], copy_write_kib=res["WRITE_SIZE"]["copy_kib"])
+    lines = [f"# HBM traffic of {args.kernel}", "", args.title, "",
+             "Commands (run from the repository root on one MI355X, one counter per pass):", "",
+             "```", args.command, "```", "",
+             f"- calibration: an elementwise copy of {args.copy_mb} MiB reads "
+             f"{summary['copy_fetch_kib']:.0f} KiB (FETCH_SIZE) and writes {summary['copy_write_kib']:.0f} KiB "
+             f"(WRITE_SIZE); factors {summary['fetch_factor']:.4f} and {summary['write_factor']:.4f}",
+             f"- {args.kernel}: {summary['launches']} launches, "
+             f"{summary['fetch_bytes_per_launch'] / 1e9:.3f} GB read and "
+             f"{summary['write_bytes_per_launch'] / 1e9:.3f} GB written per launch (calibrated)",
+             "", "```json", json.dumps(summary, indent=1), "```", ""]
+    open(args.out, "w").write("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("--csv", required=True)
+    a.add_argument("--command", required=True)
+    a.add_argument("--title", default="Kernel trace")
+    a.add_argument("--out", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--copy-mb", type=int, required=True)
+    b.add_argument("--kernel", required=True)
+    b.add_argument("--command", required=True)
+    b.add_argument("--title", default="")
+    b.add_argument("--out", required=True)
+    args = ap.parse_args()
+    (stats if args.cmd == "stats" else traffic)(args)
+
+
+if __name__ == "__main__":
+    main()
