@@ -31,6 +31,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ODF (T,P) points/s + line evals/s, FP32 vs FP64 plain at ≤1e-3 ODF err"
 
+WORKLOADS = {
+    2: ("DFSYNTHE-style table: 57 T x 25 log P at vturb 2 km/s, 1e7 synthetic lines 9 nm-10 um "
+        "(40 species x 2 stages), R=5e5 grid of 3507864 points, 1212 ramp bins x 12 sub-bins"),
+    3: ("DFSYNTHE-style table at five microturbulences: 57 T x 25 log P x vturb {0,1,2,4,8} km/s "
+        "(7125 points), 1e7 synthetic lines 9 nm-10 um (40 species x 2 stages), R=5e5 grid of "
+        "3507864 points, 1212 ramp bins x 12 sub-bins"),
+    5: ("large line list: 57 T x 25 log P x vturb {0,1,2,4,8} km/s (7125 points), 1e8 synthetic lines "
+        "9 nm-10 um (80 species x 3 stages), R=5e5 grid of 3507864 points, 1212 ramp bins x 12 sub-bins"),
+}
+
 # nominal FP32 operations per Voigt sample on the far-wing path (the path
 # almost every sample takes), FMA = 2: u carried from the previous row 2,
 # u from the index every fourth row 5/4, u^2 1, numerator 2, denominator 3,
@@ -263,6 +273,9 @@ def main():
     ap.add_argument("--batch-points", type=int, default=0, help="points per device batch (0 = automatic)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0)
+    ap.add_argument("--config", type=int, choices=sorted(WORKLOADS), default=2,
+                    help="2: the 1425-point table (default); 3: the same at five vturb (7125 points); "
+                         "5: 1e8 lines over 80 species x 3 stages (use --points and a larger --workspace-gb)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first copy a buffer of this size three times (a reference for HBM byte counters)")
     args = ap.parse_args()
@@ -287,7 +300,7 @@ def main():
         return
     from paper_2105_13611_amd import workload as W
     t0 = time.perf_counter()
-    w = W.config(2)
+    w = W.config(args.config)
     log(f"[bench] workload generated in {time.perf_counter() - t0:.1f} s: {w.lines.n_lines} lines, "
         f"{w.points.n_points} points, {w.layout.n_bins} bins")
     idx = None if args.points == 0 else stratified_points(w.points, args.points)
@@ -311,9 +324,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": head["seconds"] / head["steps"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if precs[0] == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": ("DFSYNTHE-style table: 57 T x 25 log P at vturb 2 km/s, 1e7 synthetic lines "
-                                "9 nm-10 um (40 species x 2 stages), R=5e5 grid of 3507864 points, "
-                                "1212 ramp bins x 12 sub-bins")
+        "config": {"workload": WORKLOADS[args.config]
                    + ("" if idx is None else f" [stratified subset of {n_pts} points]"),
                    "points": n_pts, "lines": w.lines.n_lines, "grid_points": int(w.layout.bin_edges[-1]),
                    "bins": w.layout.n_bins, "sub_bins": w.layout.n_steps},

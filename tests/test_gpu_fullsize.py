@@ -5,6 +5,8 @@ benchmark table, computed with the benchmark's workspace (64-point device
 batches), at sampled (T, P, v_turb) points that span the grid's cost range;
 the oracle checks a few bins of each (it needs minutes per point for all).
 """
+from dataclasses import replace
+
 import numpy as np
 import pytest
 
@@ -70,3 +72,43 @@ def test_full_size_sampled_parity(full, reference, prec):
     assert np.all(np.isfinite(got)) and np.all(got > 0)
     # monotone steps in every bin of every point (any size property)
     assert np.all(np.diff(got, axis=2) >= -1e-6 * np.abs(got[:, :, 1:]))
+
+
+@pytest.mark.slow
+def test_large_line_list_sampled_parity():
+    """The 1e8-line list over 80 species x 3 stages, at two points and two
+    bins.  The device sums all 1e8 lines; the oracle only needs the lines
+    whose windows can reach the sampled bins: a window spans at most 500
+    Doppler widths, under 3.2 % in wavelength on this grid (2e5 K, 12 amu,
+    8 km/s), so lines within 5 % of a bin's wavelengths are a superset."""
+    import torch
+    from paper_2105_13611_amd import odf
+    w = W.config(5, n_requests=1)
+    assert w.lines.n_lines == 100_000_000 and w.species.n_stages == 3
+    pts = W.Points(np.array([4000.0, 100000.0]), np.array([2.0, -2.0]), np.array([2.0, 8.0]))
+    bins = [150, 800]
+    a = w.requests[0].abundance
+    with odf.plan_for(w, precision="mixed", workspace_bytes=24 << 30) as plan:
+        out, st = plan.compute(a, pts)
+        got = out.double().cpu().numpy()
+    torch.cuda.synchronize()
+    e = w.layout.bin_edges
+    lam = w.lines.lambda_nm
+    worst, skipped = 0.0, 0
+    for b in bins:
+        l0 = oracle.grid_lambda_nm(w.layout, e[b])
+        l1 = oracle.grid_lambda_nm(w.layout, e[b + 1] - 1)
+        sub = replace(w, lines=w.lines.take(np.nonzero((lam > l0 / 1.05) & (lam < l1 * 1.05))[0]))
+        for i in range(pts.n_points):
+            steps, _, ex = oracle.odf_point(sub.lines, w.species, a, float(pts.T_K[i]), float(pts.log10_P[i]),
+                                            float(pts.vturb_kms[i]), w.layout, w.options, [b])
+            if b in ambiguous_bins(ex["lq"], e):
+                skipped += 1
+                continue
+            worst = max(worst, float(rel_err(got[i, b], steps[0]).max()))
+    print(f"1e8 lines: max rel err per step {worst:.3e}, skipped {skipped}, survivors {st['survivors']}, "
+          f"samples {st['voigt_samples']}")
+    assert skipped <= 1
+    assert worst <= TOL["mixed"]
+    assert st["line_evals"] == 2 * 100_000_000
+    assert np.all(np.isfinite(got)) and np.all(got > 0)

@@ -179,6 +179,27 @@ def test_end_to_end_multi_tile_multi_point(odf, multi, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_end_to_end_three_stages_request_composition(odf, prec):
+    """80 species x 3 ionisation stages (the Saha chain beyond one step),
+    with a request's own scaled composition ([M/H], [alpha/Fe])."""
+    w = W.config(5, n_lines=40_000, lam_range=(300.0, 345.0), n_bins=7, n_requests=1)
+    w = replace(w, points=W.Points(np.array([2500.0, 6000.0, 15000.0, 60000.0, 200000.0]),
+                                   np.array([6.0, -2.0, 3.0, 8.0, -4.0]),
+                                   np.array([1.0, 2.0, 0.0, 8.0, 4.0])))
+    assert w.species.n_stages == 3 and w.species.n_species == 80
+    a = w.requests[0].abundance
+    assert not np.allclose(a, w.species.abundance)
+    with odf.plan_for(w, precision=prec, workspace_bytes=64 << 20) as plan:
+        out, st = plan.compute(a, w.points)
+        out = out.double().cpu().numpy()
+    worst, worst_log, skipped = _compare_points(w, out, prec, abundance=a)
+    print(f"three stages {prec}: max rel err {worst:.3e}, max |dlog10 k| {worst_log:.3e}, "
+          f"skipped {skipped}, survivors {st['survivors']}")
+    assert skipped <= 2
+    assert worst <= TOL_STEP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_deterministic(plans1, cfg1, prec):
     w = cfg1
     a, _ = plans1[prec].compute(w.species.abundance, w.points)
