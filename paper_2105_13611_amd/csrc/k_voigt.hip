@@ -199,26 +199,29 @@ __device__ __forceinline__ float x_of_d32(float d, const Far32& f) {
 
 // Far rows wholly inside the window, given as a bit mask of the wave's 16
 // rows (all 16 when the window covers the tile and no row is near the core).
-// Rows go in groups of four: u is taken from the index at the start of a
+// Rows go in groups of eight: u is taken from the index at the start of a
 // group and carried to the next row by the exact frequency ratio q^-64 (one
-// FMA).  A row of a group that is not in the mask gets A = B = 0 (scalar
-// selects), so it adds an exact zero at no extra vector cost; groups with
-// no row in the mask are skipped.  This is the only place that updates the
-// register sums, so they stay in one set of registers.
+// FMA; the rounding this accumulates over seven rows stays below 1e-6 of
+// u).  A row of a group that is not in the mask gets K2 = +inf (a scalar
+// select), so its reciprocal is exactly zero and it adds nothing, at no extra
+// vector cost; groups with no row in the mask are skipped.  This is the only
+// place that updates the register sums, so they stay in one set of
+// registers.
 __device__ __forceinline__ void rows32(unsigned rows, float d0, float q64, const Far32& f,
                                        float (&p)[kRows]) {
+  constexpr int kGroup = 8;
+  const int inf = 0x7f800000;
 #pragma unroll
-  for (int g = 0; g < kRows; g += 4) {
-    const unsigned gm = (rows >> g) & 0xfu;
+  for (int g = 0; g < kRows; g += kGroup) {
+    const unsigned gm = (rows >> g) & ((1u << kGroup) - 1u);
     if (!gm) continue;
     float u = x_of_d32(d0 - (float)(64 * g), f);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int on = -(int)((gm >> r) & 1u);   // all ones or zero (uniform)
-      const float A = __int_as_float(__float_as_int(f.A) & on);
-      const float B = __int_as_float(__float_as_int(f.B) & on);
+    for (int r = 0; r < kGroup; ++r) {
+      const int K2 = ((gm >> r) & 1u) ? __float_as_int(f.K2) : inf;   // uniform
       const float u2 = u * u;
-      p[g + r] = fmaf(fmaf(u2, A, B), __builtin_amdgcn_rcpf(fmaf(u2, u2 + f.K1, f.K2)), p[g + r]);
+      const float den = fmaf(u2, u2 + f.K1, __int_as_float(K2));
+      p[g + r] = fmaf(fmaf(u2, f.A, f.B), __builtin_amdgcn_rcpf(den), p[g + r]);
       u = fmaf(u, q64, f.step);
     }
   }
