@@ -426,12 +426,11 @@ __device__ __forceinline__ double core64(double x, double y, double ep, const Qu
   const double hx = x * invh;
   const double fr = hx - rint(hx);
   const bool sh = fabs(fr) < 0.25;
-  const double delta = sh ? 0.5 : 0.0;
+  const double xs = sh ? x - 0.5 * h : x;   // x - delta h: node k then sits at k h
   double num = 0.0, den = 1.0;
 #pragma unroll
   for (int k = -kTrap64Half; k <= kTrap64Half; ++k) {
-    const double t = ((double)k + delta) * h;
-    const double dd = x - t;
+    const double dd = xs - (double)k * h;
     const double D = fma(dd, dd, y2);
     const double ck = sh ? Q->tr64_ch[k + kTrap64Half] : Q->tr64_ci[k + kTrap64Half];
     num = fma(num, D, ck * den);
