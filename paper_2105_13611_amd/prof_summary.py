@@ -5,6 +5,9 @@
   python -m paper_2105_13611_amd.prof_summary traffic --fetch <counter csv>
       --write <counter csv> --copy-mb 1024 --kernel k_voigt32
       --command "<profiled command>" --out profiles/<name>.md
+  python -m paper_2105_13611_amd.prof_summary flops --csv <counter csv>
+      --bench-log <the profiled run's output> --kernel k_voigt32
+      --command "<profiled command>" --out profiles/<name>.md
 
 `traffic` scales each kernel's FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
 by the ratio of the bytes a plain elementwise copy of known size moves to what
@@ -95,6 +98,37 @@ def traffic(args):
     open(args.out, "w").write("\n".join(lines))
 
 
+def flops(args):
+    """Executed floating-point operations of one kernel from the VALU counters
+    (wave instructions x 64 lanes; FMA = 2), per Voigt sample of the profiled
+    run (the samples come from that run's benchmark line)."""
+    counters = defaultdict(float)
+    launches = set()
+    for r in csv.DictReader(open(args.csv)):
+        if args.kernel in r["Kernel_Name"]:
+            counters[r["Counter_Name"]] += float(r["Counter_Value"])
+            launches.add(r["Dispatch_Id"])
+    line = [l for l in open(args.bench_log) if l.startswith("{")][-1]
+    j = json.loads(line)
+    samples = j["voigt_samples_per_point"] * j["config"]["points"] * j["steps"]
+    suffix = "F32" if "32" in args.kernel else "F64"
+    weight = {f"SQ_INSTS_VALU_ADD_{suffix}": 1, f"SQ_INSTS_VALU_MUL_{suffix}": 1,
+              f"SQ_INSTS_VALU_FMA_{suffix}": 2, f"SQ_INSTS_VALU_TRANS_{suffix}": 1}
+    flop = sum(64.0 * counters[k] * w for k, w in weight.items())
+    per_sample = flop / samples
+    rate = per_sample * j["voigt_samples_per_s"] / 1e12 if "voigt_samples_per_s" in j else None
+    lines = [f"# Executed {suffix} operations of {args.kernel}", "", args.title, "",
+             "Command (run from the repository root on one MI355X):", "", "```", args.command, "```", "",
+             "| counter | wave instructions | per Voigt sample (x64 lanes) |", "|---|---|---|"]
+    for k in sorted(counters):
+        lines.append(f"| {k} | {counters[k]:.4e} | {64.0 * counters[k] / samples:.3f} |")
+    lines += ["", f"- {len(launches)} launches, {samples:.4e} Voigt samples",
+              f"- executed {suffix} FLOP per sample (FMA = 2, all 64 lanes counted): {per_sample:.2f}",
+              f"- at the profiled run's sample rate ({j.get('voigt_samples_per_s', 0):.4e}/s, which the "
+              f"profiler slows): {rate:.2f} TFLOP/s" if rate else ""]
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -111,8 +145,15 @@ def main():
     b.add_argument("--command", required=True)
     b.add_argument("--title", default="")
     b.add_argument("--out", required=True)
+    c = sub.add_parser("flops")
+    c.add_argument("--csv", required=True)
+    c.add_argument("--bench-log", required=True)
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--title", default="")
+    c.add_argument("--out", required=True)
     args = ap.parse_args()
-    (stats if args.cmd == "stats" else traffic)(args)
+    {"stats": stats, "traffic": traffic, "flops": flops}[args.cmd](args)
 
 
 if __name__ == "__main__":

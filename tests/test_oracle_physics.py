@@ -61,6 +61,31 @@ def test_saha_structure_by_regression():
     assert math.exp(c0) * ne == pytest.approx(2 * U1 / U0 * GOLD["saha_constant_cm3_K32"]["value"], rel=1e-4)
 
 
+def test_saha_three_stages():
+    """The chain beyond one step: the second ratio follows the Saha law with
+    its own potential (regression on T recovers 3/2 and chi_2), a third stage
+    that cannot be reached reduces the result to the two-stage one, and the
+    limits put everything in the lowest or the highest stage."""
+    chi = np.array([[7.9, 16.2]])
+    U = np.array([[25.0, 30.0, 12.0]])
+    ne = 1e13
+    Ts = np.array([6000.0, 9000.0, 14000.0, 21000.0, 30000.0])
+    y = [math.log(stage_fractions(T, ne, chi, U)[0, 2] / stage_fractions(T, ne, chi, U)[0, 1]) for T in Ts]
+    A = np.stack([np.ones_like(Ts), np.log(Ts), 1.0 / Ts], axis=1)
+    c0, c1, c2 = np.linalg.lstsq(A, np.array(y), rcond=None)[0]
+    assert c1 == pytest.approx(1.5, abs=1e-8)
+    assert -c2 / GOLD["electron_volt_over_k_K"]["value"] == pytest.approx(16.2, rel=1e-9)
+    assert math.exp(c0) * ne == pytest.approx(2 * 12.0 / 30.0 * GOLD["saha_constant_cm3_K32"]["value"], rel=1e-4)
+    for T in [4000.0, 8000.0, 15000.0]:
+        f3 = stage_fractions(T, ne, np.array([[7.9, 1e4]]), U)
+        f2 = stage_fractions(T, ne, np.array([[7.9]]), U[:, :2])
+        np.testing.assert_allclose(f3[:, :2], f2, rtol=1e-13)
+        assert f3[0, 2] < 1e-300
+        np.testing.assert_allclose(stage_fractions(T, ne, chi, U).sum(), 1.0, rtol=1e-14)
+    assert stage_fractions(1500.0, 1e15, chi, U)[0, 0] > 0.999
+    assert stage_fractions(5e6, 1e8, chi, U)[0, 2] > 0.999
+
+
 def test_population_mass_balance():
     sp = W.config(1).species
     st = point_state(5000.0, 4.0, 0.1, sp.abundance, sp.mass_amu)
