@@ -287,7 +287,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--points", type=int, default=0, help="stratified subset (0 = whole table)")
-    ap.add_argument("--workspace-gb", type=float, default=40.0)
+    ap.add_argument("--workspace-gb", type=float, default=80.0)
     ap.add_argument("--batch-points", type=int, default=0, help="points per device batch (0 = automatic)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0)

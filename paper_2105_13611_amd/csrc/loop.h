@@ -17,6 +17,11 @@ namespace odf {
 
 SlotLayout make_slot(const odf_plan_s* p, int32_t pts);
 Batch make_batch(const odf_plan_s* p, const SlotLayout& s, char* base, int32_t n_points);
+// The per-batch chain: preparation (point state, selection, scan, survivor
+// emission) then summation (Voigt scatter-sum, ODF reduction into `out`).
+odf_status enqueue_prep(odf_plan_s* p, const Batch& B, hipStream_t st, StageTimer* timer = nullptr);
+odf_status enqueue_sum(odf_plan_s* p, const Batch& B, char* slot_base, const SlotLayout& s,
+                       void* out, hipStream_t st, StageTimer* timer = nullptr);
 odf_status enqueue_batch(odf_plan_s* p, const Batch& B, char* slot_base, const SlotLayout& s,
                          void* out, hipStream_t st, StageTimer* timer = nullptr);
 odf_status validate_request(const odf_plan_s* p, const odf_request* r, bool need_out);

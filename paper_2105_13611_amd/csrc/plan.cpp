@@ -72,6 +72,25 @@ void free_owned(odf_plan_s* p) {
   p->owned.clear();
 }
 
+// Streams and events of the odf_compute pipeline (null handles skipped).
+void release_streams(odf_plan_s* p) {
+  if (p->prep_stream) (void)hipStreamDestroy(p->prep_stream);
+  for (hipStream_t& st : p->sum_stream)
+    if (st) (void)hipStreamDestroy(st);
+  for (hipEvent_t& e : p->ev_join)
+    if (e) (void)hipEventDestroy(e);
+  for (int k = 0; k < kPipeSlots; ++k) {
+    if (p->ev_prep[k]) (void)hipEventDestroy(p->ev_prep[k]);
+    if (p->ev_free[k]) (void)hipEventDestroy(p->ev_free[k]);
+  }
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  p->prep_stream = nullptr;
+  p->sum_stream[0] = p->sum_stream[1] = nullptr;
+  p->ev_fork = nullptr;
+  for (hipEvent_t& e : p->ev_join) e = nullptr;
+  for (int k = 0; k < kPipeSlots; ++k) p->ev_prep[k] = p->ev_free[k] = nullptr;
+}
+
 odf_status validate_layout(const odf_layout* L, int64_t* N_out) {
   if (!L) { set_error("layout is NULL"); return ODF_E_INVALID; }
   const int64_t N = grid_points(L->lambda_first_nm, L->lambda_last_nm, L->resolving_power);
@@ -257,12 +276,16 @@ struct TimedLaunch {
 
 }  // namespace
 
-odf_status enqueue_batch(odf_plan_s* p, const Batch& B, char* slot_base, const SlotLayout& s,
-                         void* out, hipStream_t st, StageTimer* timer) {
+odf_status enqueue_prep(odf_plan_s* p, const Batch& B, hipStream_t st, StageTimer* timer) {
   { TimedLaunch tl(timer, st, 0); HIP_TRY(launch_point_state(st, p->params, B)); }
   { TimedLaunch tl(timer, st, 1); HIP_TRY(launch_select(st, p->params, p->lines, B)); }
   { TimedLaunch tl(timer, st, 2); HIP_TRY(launch_scan(st, p->params, p->lines, B)); }
   { TimedLaunch tl(timer, st, 3); HIP_TRY(launch_emit(st, p->params, p->lines, B, p->opts.precision == ODF_PREC_FP64)); }
+  return ODF_OK;
+}
+
+odf_status enqueue_sum(odf_plan_s* p, const Batch& B, char* slot_base, const SlotLayout& s,
+                       void* out, hipStream_t st, StageTimer* timer) {
   { TimedLaunch tl(timer, st, 4); HIP_TRY(launch_voigt(st, p->params, B, p->d_quad)); }
   if (out) {
     TimedLaunch tl(timer, st, 5);
@@ -270,6 +293,13 @@ odf_status enqueue_batch(odf_plan_s* p, const Batch& B, char* slot_base, const S
                        slot_base + s.off_gscr, p->d_goff, p->gscr_elems));
   }
   return ODF_OK;
+}
+
+odf_status enqueue_batch(odf_plan_s* p, const Batch& B, char* slot_base, const SlotLayout& s,
+                         void* out, hipStream_t st, StageTimer* timer) {
+  const odf_status e = enqueue_prep(p, B, st, timer);
+  if (e != ODF_OK) return e;
+  return enqueue_sum(p, B, slot_base, s, out, st, timer);
 }
 
 // After the streams have drained: add the recorded pairs to the totals.
@@ -566,22 +596,42 @@ odf_status odf_plan(const odf_lines* lines, const odf_species* species, const od
   while (pts > 1 && make_slot(p.get(), pts).bytes > p->opts.workspace_bytes) --pts;
   p->compute_points = std::max(pts, 1);
   p->compute_slot = make_slot(p.get(), p->compute_points);
-  // two lanes of half the points when the workspace holds two slots of >= 8 points
-  if (p->compute_points >= 16) {
-    const SlotLayout half = make_slot(p.get(), p->compute_points / 2);
-    if (2 * half.bytes <= p->opts.workspace_bytes) {
-      bool ok = true;
-      for (int k = 0; k < 2 && ok; ++k)
-        ok = hipStreamCreateWithFlags(&p->lane_stream[k], hipStreamNonBlocking) == hipSuccess &&
-             hipEventCreateWithFlags(&p->ev_join[k], hipEventDisableTiming) == hipSuccess;
-      ok = ok && hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess;
-      if (!ok) {
-        set_error("stream or event creation failed");
-        free_owned(p.get());
-        return ODF_E_DEVICE;
+  // odf_compute pipeline: the most slots (up to kPipeSlots) of equal size
+  // that the workspace holds, each with as many points as fit (at most one
+  // batch's worth)
+  {
+    const int32_t pmax = p->opts.max_batch_points > 0 ? std::min(p->opts.max_batch_points, kMaxBatch) : kMaxBatch;
+    int32_t slots = 0, spts = 0;
+    for (int ns = kPipeSlots; ns >= 1 && slots == 0; --ns) {
+      const int64_t avail = p->opts.workspace_bytes / ns - p->fixed_bytes;
+      if (avail < p->per_point_bytes) continue;
+      int32_t q = (int32_t)std::min<int64_t>(avail / std::max<int64_t>(p->per_point_bytes, 1), pmax);
+      while (q > 1 && (int64_t)ns * make_slot(p.get(), q).bytes > p->opts.workspace_bytes) --q;
+      if ((int64_t)ns * make_slot(p.get(), q).bytes <= p->opts.workspace_bytes) {
+        slots = ns;
+        spts = q;
       }
-      p->compute_lanes = 2;
-      p->lane_slot = half;
+    }
+    if (slots == 0) {   // one point fits (checked above), so this is one slot of one point
+      slots = 1;
+      spts = 1;
+    }
+    p->pipe_slots = slots;
+    p->pipe_slot = make_slot(p.get(), spts);
+    bool ok = hipStreamCreateWithFlags(&p->prep_stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < 2 && ok; ++k)
+      ok = hipStreamCreateWithFlags(&p->sum_stream[k], hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; k < 3 && ok; ++k)
+      ok = hipEventCreateWithFlags(&p->ev_join[k], hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < slots && ok; ++k)
+      ok = hipEventCreateWithFlags(&p->ev_prep[k], hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&p->ev_free[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      set_error("stream or event creation failed");
+      release_streams(p.get());
+      free_owned(p.get());
+      return ODF_E_DEVICE;
     }
   }
   p->loop.reset(new RequestLoop(p.get()));
@@ -614,11 +664,7 @@ odf_status odf_plan_destroy(odf_plan_t* plan) {
   plan->loop.reset();  // drains and joins the request loop
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : plan->timer.pool) (void)hipEventDestroy(e);
-  for (int k = 0; k < 2; ++k) {
-    if (plan->lane_stream[k]) (void)hipStreamDestroy(plan->lane_stream[k]);
-    if (plan->ev_join[k]) (void)hipEventDestroy(plan->ev_join[k]);
-  }
-  if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+  release_streams(plan);
   if (plan->pinned) (void)hipHostFree(plan->pinned);
   free_owned(plan);
   delete plan;
@@ -635,8 +681,8 @@ odf_status odf_compute(odf_plan_t* p, const odf_request* r, odf_stats* stats) {
   WorkspaceLease lease(p->loop.get());   // the request loop is idle while this runs
   hipStream_t s = static_cast<hipStream_t>(p->opts.stream);
   char* base = static_cast<char*>(p->opts.workspace);
-  const int lanes = p->compute_lanes;
-  const SlotLayout& sl = lanes == 2 ? p->lane_slot : p->compute_slot;
+  const int NS = p->pipe_slots;
+  const SlotLayout& sl = p->pipe_slot;
   const int n = r->n_points;
   const int S = p->n_species;
   // pinned host staging: point arrays and abundances in, counters out
@@ -658,39 +704,57 @@ odf_status odf_compute(odf_plan_t* p, const odf_request* r, odf_stats* stats) {
   std::memcpy(hP, r->log10_P_cgs, 8 * (size_t)n);
   std::memcpy(hV, r->vturb_kms, 8 * (size_t)n);
   std::memcpy(hA, r->abundance, 8 * (size_t)S);
-  hipStream_t ls[2] = {s, s};
-  if (lanes == 2) {
-    HIP_TRY(hipEventRecord(p->ev_fork, s));
-    for (int k = 0; k < 2; ++k) {
-      ls[k] = p->lane_stream[k];
-      HIP_TRY(hipStreamWaitEvent(ls[k], p->ev_fork, 0));
-    }
-  }
-  for (int k = 0; k < lanes; ++k)
-    HIP_TRY(hipMemcpyAsync(base + k * sl.bytes + sl.off_abund, hA, 8 * S, hipMemcpyHostToDevice, ls[k]));
+  // fork the pipeline's streams from the caller's stream
+  hipStream_t ps = p->prep_stream;
+  hipStream_t vs[2] = {p->sum_stream[0], p->sum_stream[1]};
+  HIP_TRY(hipEventRecord(p->ev_fork, s));
+  HIP_TRY(hipStreamWaitEvent(ps, p->ev_fork, 0));
+  HIP_TRY(hipStreamWaitEvent(vs[0], p->ev_fork, 0));
+  HIP_TRY(hipStreamWaitEvent(vs[1], p->ev_fork, 0));
   const size_t osz = (p->opts.precision == ODF_PREC_MIXED ? 4 : 8);
-  int batch = 0;
-  for (int b0 = 0; b0 < n; b0 += sl.points, ++batch) {
-    const int k = batch % lanes;
-    hipStream_t lst = ls[k];
-    char* sb = base + k * sl.bytes;
-    const int nb = std::min(sl.points, n - b0);
-    HIP_TRY(hipMemcpyAsync(sb + sl.off_T, hT + b0, 8 * nb, hipMemcpyHostToDevice, lst));
-    HIP_TRY(hipMemcpyAsync(sb + sl.off_logP, hP + b0, 8 * nb, hipMemcpyHostToDevice, lst));
-    HIP_TRY(hipMemcpyAsync(sb + sl.off_vt, hV + b0, 8 * nb, hipMemcpyHostToDevice, lst));
-    Batch B = make_batch(p, sl, sb, nb);
-    char* outp = static_cast<char*>(r->out) + (size_t)b0 * p->n_bins * p->n_steps * osz;
-    odf_status es = enqueue_batch(p, B, sb, sl, outp, lst, p->opts.kernel_timing ? &p->timer : nullptr);
-    if (es != ODF_OK) return es;
-    HIP_TRY(hipMemcpyAsync(h_nsurv + b0, B.nsurv, 4 * nb, hipMemcpyDeviceToHost, lst));
-    HIP_TRY(hipMemcpyAsync(h_nsamp + b0, B.nsamp, 8 * nb, hipMemcpyDeviceToHost, lst));
-  }
-  if (lanes == 2) {
-    for (int k = 0; k < 2; ++k) {
-      HIP_TRY(hipEventRecord(p->ev_join[k], ls[k]));
-      HIP_TRY(hipStreamWaitEvent(s, p->ev_join[k], 0));
+  StageTimer* timer = p->opts.kernel_timing ? &p->timer : nullptr;
+  auto enqueue_all = [&]() -> odf_status {
+    for (int k = 0; k < NS; ++k)
+      HIP_TRY(hipMemcpyAsync(base + k * sl.bytes + sl.off_abund, hA, 8 * S, hipMemcpyHostToDevice, ps));
+    int batch = 0;
+    for (int b0 = 0; b0 < n; b0 += sl.points, ++batch) {
+      const int k = batch % NS;
+      char* sb = base + k * sl.bytes;
+      const int nb = std::min(sl.points, n - b0);
+      // preparation, once the slot's previous batch has been reduced
+      if (batch >= NS) HIP_TRY(hipStreamWaitEvent(ps, p->ev_free[k], 0));
+      HIP_TRY(hipMemcpyAsync(sb + sl.off_T, hT + b0, 8 * nb, hipMemcpyHostToDevice, ps));
+      HIP_TRY(hipMemcpyAsync(sb + sl.off_logP, hP + b0, 8 * nb, hipMemcpyHostToDevice, ps));
+      HIP_TRY(hipMemcpyAsync(sb + sl.off_vt, hV + b0, 8 * nb, hipMemcpyHostToDevice, ps));
+      Batch B = make_batch(p, sl, sb, nb);
+      odf_status es = enqueue_prep(p, B, ps, timer);
+      if (es != ODF_OK) return es;
+      HIP_TRY(hipMemcpyAsync(h_nsurv + b0, B.nsurv, 4 * nb, hipMemcpyDeviceToHost, ps));
+      HIP_TRY(hipMemcpyAsync(h_nsamp + b0, B.nsamp, 8 * nb, hipMemcpyDeviceToHost, ps));
+      HIP_TRY(hipEventRecord(p->ev_prep[k], ps));
+      // summation on the summing streams in turn
+      hipStream_t v = vs[batch & 1];
+      HIP_TRY(hipStreamWaitEvent(v, p->ev_prep[k], 0));
+      char* outp = static_cast<char*>(r->out) + (size_t)b0 * p->n_bins * p->n_steps * osz;
+      es = enqueue_sum(p, B, sb, sl, outp, v, timer);
+      if (es != ODF_OK) return es;
+      HIP_TRY(hipEventRecord(p->ev_free[k], v));
     }
+    return ODF_OK;
+  };
+  const odf_status est = enqueue_all();
+  if (est != ODF_OK) {
+    // whatever was enqueued still reads the staging buffers: let it drain
+    (void)hipStreamSynchronize(ps);
+    (void)hipStreamSynchronize(vs[0]);
+    (void)hipStreamSynchronize(vs[1]);
+    return est;
   }
+  // join back into the caller's stream
+  HIP_TRY(hipEventRecord(p->ev_join[0], ps));
+  HIP_TRY(hipEventRecord(p->ev_join[1], vs[0]));
+  HIP_TRY(hipEventRecord(p->ev_join[2], vs[1]));
+  for (hipEvent_t e : p->ev_join) HIP_TRY(hipStreamWaitEvent(s, e, 0));
   HIP_TRY(hipStreamSynchronize(s));
   if (p->opts.kernel_timing) collect_timer(p->timer);
   if (stats) {

@@ -30,6 +30,9 @@ struct SlotLayout {
   int32_t points;     // points per slot
 };
 
+// Slots of the odf_compute pipeline (at most).
+constexpr int kPipeSlots = 4;
+
 // HIP-event timing of the kernels that odf_compute launches (opt-in).
 constexpr int kStages = 6;
 struct StageTimer {
@@ -72,15 +75,22 @@ struct odf_plan_s {
   int64_t per_point_bytes = 0;
   int64_t fixed_bytes = 0;
   int32_t compute_points = 0;       // points per odf_compute batch
-  odf::SlotLayout compute_slot{};
-  odf::SlotLayout lane_slot{};      // slot of one lane when compute_lanes == 2
-  // odf_compute alternates batches over `compute_lanes` internal streams,
-  // each with its own slot of the workspace, forked from and joined back to
-  // options.stream, so one batch's selection and sort overlap another's
-  // Voigt kernel and launch tails
-  int32_t compute_lanes = 1;
-  hipStream_t lane_stream[2] = {nullptr, nullptr};
-  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  odf::SlotLayout compute_slot{};   // one batch of compute_points (stage entry points)
+  // odf_compute pipeline: `pipe_slots` slots of `pipe_slot.points` points.
+  // A preparation stream fills slot b % pipe_slots with batch b (point
+  // state, selection, scan, emission) as soon as the slot is free; two
+  // summing streams take the batches alternately (Voigt scatter-sum, ODF
+  // reduction).  All three fork from and join back to options.stream, so the
+  // Voigt kernels of consecutive batches overlap each other's tails and the
+  // next batches' preparation never waits behind a Voigt kernel.
+  int32_t pipe_slots = 1;
+  odf::SlotLayout pipe_slot{};
+  hipStream_t prep_stream = nullptr;
+  hipStream_t sum_stream[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_prep[odf::kPipeSlots] = {};   // batch of the slot prepared
+  hipEvent_t ev_free[odf::kPipeSlots] = {};   // slot summed and reduced
   void* pinned = nullptr;           // host staging of point arrays and counters
   size_t pinned_bytes = 0;
 

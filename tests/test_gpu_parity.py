@@ -200,6 +200,24 @@ def test_end_to_end_three_stages_request_composition(odf, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batching_and_pipeline_slots_do_not_change_results(odf, multi, prec):
+    """odf_compute splits the points into batches over up to four workspace
+    slots (preparation and summation on different streams, slots reused in
+    turn).  Each point is computed on its own, so every split must give the
+    same bits: one batch, batches of one and two points (slots reused, ragged
+    end), and a workspace of only a few points."""
+    w = multi
+    outs = []
+    for ws, mb in [(256 << 20, 0), (24 << 20, 1), (24 << 20, 4), (12 << 20, 0)]:
+        with odf.plan_for(w, precision=prec, workspace_bytes=ws, max_batch_points=mb) as plan:
+            out, st = plan.compute(w.species.abundance, w.points)
+            outs.append(out.clone())
+            assert st["points"] == w.points.n_points
+    for o in outs[1:]:
+        assert bool((o == outs[0]).all())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_deterministic(plans1, cfg1, prec):
     w = cfg1
     a, _ = plans1[prec].compute(w.species.abundance, w.points)
