@@ -44,8 +44,8 @@ WORKLOADS = {
 # nominal FP32 operations per Voigt sample on the far-wing path (the path
 # almost every sample takes), FMA = 2: u carried from the previous row 2,
 # u from the index at the first of eight rows 6/8, u^2 1, numerator 2,
-# denominator 3, reciprocal 1, accumulate 2, compensated add every 16 lines 4/16
-FLOP_PER_SAMPLE_F32 = 12.0
+# denominator 3, reciprocal 1, accumulate 2, compensated add every 64 lines 4/64
+FLOP_PER_SAMPLE_F32 = 11.8
 # FP64 far wing (four-node pair): x carried 2, x^2 1, r^2 1, two pairs
 # 2*(1+1+2), numerator 5, product 1, reciprocal with two Newton steps 9,
 # scale 4, accumulate 1
