@@ -40,12 +40,12 @@ constexpr float kTrap32H = 0.75f;
 constexpr float kTrap32Tmax = 4.2f;
 // FP64: rows with all |x| >= 40 -> four-node Gauss-Hermite pair sum (relative
 // error below 3e-12); all |x| >= 10 -> eight-node (below 5e-13); other rows ->
-// trapezoid h = 0.5, nodes |t| <= 6, for every lane.
+// trapezoid h = 0.55, nodes |t| <= 5.9 (below 1.2e-13), for every lane.
 constexpr double kFarR64 = 10.0;
 constexpr double kFar4R64 = 40.0;
-constexpr int kTrap64Half = 12;                  // k = -12..12
-constexpr double kTrap64H = 0.5;
-constexpr double kTrap64Tmax = 6.0;
+constexpr int kTrap64Half = 11;                  // k = -11..11
+constexpr double kTrap64H = 0.55;
+constexpr double kTrap64Tmax = 5.9;
 
 // FP32 small-damping form for rows near the core of lines with a < 0.4:
 //   H(x, a) = e^{a^2 - x^2} cos(2 x a) + sum_k a^{2k+1} T_{2k+1}(x),
