@@ -171,8 +171,14 @@ odf_status odf_plan(const odf_lines *lines, const odf_species *species,
                     odf_plan_t **out);
 
 /* Compute one request on options.stream and wait for it (App. E, stages one
- * to three for every point).  Must not run concurrently with another
- * odf_compute on the same plan.  stats may be NULL. */
+ * to three for every point).  The points go in batches through up to four
+ * slots of the workspace: an internal preparation stream runs the line
+ * selection of upcoming batches while two internal summing streams run the
+ * Voigt sums and ODF reductions of earlier ones; all three are ordered after
+ * the work already on options.stream, and options.stream waits for them
+ * before this returns.  Results do not depend on the batching.  Must not run
+ * concurrently with another odf_compute on the same plan; the request loop
+ * pauses while it runs.  stats may be NULL. */
 odf_status odf_compute(odf_plan_t *plan, const odf_request *req, odf_stats *stats);
 
 /* Queue a request for the plan's request loop and return at once.  The host
@@ -231,7 +237,7 @@ odf_status odf_stage_reduce(odf_plan_t *plan, const void *kappa_dev, void *out_d
  * emission, 4 Voigt scatter-sum, 5 ODF reduction.  All arrays are host
  * [6], caller-owned.  ms receives the summed HIP-event durations of the
  * launches in milliseconds; busy_ms the length of the union of their
- * intervals (less than ms when odf_compute's two internal streams run
+ * intervals (less than ms when odf_compute's internal streams run
  * launches of one stage at the same time); launches the launch counts.
  * reset nonzero clears the totals afterwards.  ODF_E_INVALID for a NULL
  * argument. */

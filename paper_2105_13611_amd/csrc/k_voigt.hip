@@ -35,11 +35,7 @@ namespace odf {
 
 namespace {
 
-constexpr float kInvSqrtPiF = 0.56418958354775628695f;
 constexpr float kPiF = 3.14159265358979323846f;
-constexpr float kSqrtPiF = 1.77245385090551602730f;
-// waves per SIMD the FP32 kernel is compiled for (VGPR budget 512 / waves)
-constexpr int kMinWaves32 = 1;
 
 // Workgroup order.  The hardware deals consecutive workgroups round-robin
 // to the 8 XCDs, so consecutive tiles of a point land on different XCDs and
