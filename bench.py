@@ -100,10 +100,27 @@ def run_gpu(w, precision, steps, warmup, workspace_gb, points_idx=None, batch_po
     res = dict(precision=precision, seconds=dt, steps=steps, n_points=pts.n_points,
                plan_seconds=t_plan, stats=stats, stage_ms=times,
                batch_points=None, checksum=float(out.double().sum().item()))
+    res["kernel_alone"] = kernel_alone(plan, w)
     plan.destroy()
     del out
     torch.cuda.empty_cache()
     return res
+
+
+def kernel_alone(plan, w, n_points=72, chunk=24):
+    """The Voigt kernel with nothing beside it: requests of `chunk` points are
+    one batch each, so preparation, Voigt and reduction run one after the
+    other and each Voigt launch has the GPU to itself.  Stratified points of
+    the table, outside the timed region."""
+    pts = w.points.take(stratified_points(w.points, n_points))
+    plan.stage_times(reset=True)
+    samples = 0
+    for i in range(0, pts.n_points, chunk):
+        _, st = plan.compute(w.species.abundance, pts.take(slice(i, i + chunk)))
+        samples += st["voigt_samples"]
+    t = plan.stage_times(reset=True)["voigt"]
+    return dict(ms=t["ms"], busy_ms=t["busy_ms"], launches=t["launches"], samples=samples,
+                points=pts.n_points, batch_points=chunk)
 
 
 def kernel_sources_sha256():
@@ -145,11 +162,20 @@ def roofline(res, flop_per_sample, precision):
     # taken over the union of the kernel's launch intervals
     flop_per_launch = samples * flop_per_sample / launches
     achieved = flop_per_launch / (busy / 1e3 / launches) / 1e12
-    return dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
-                frac=achieved / PEAK_VALU_TFLOPS, traffic=traffic_per_launch(precision),
-                kernel="voigt scatter-sum", avg_launch_ms=ms / launches,
-                busy_ms_per_launch=busy / launches, launches=launches,
-                samples_per_launch=samples / launches, flop_per_sample=flop_per_sample)
+    out = dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
+               frac=achieved / PEAK_VALU_TFLOPS, traffic=traffic_per_launch(precision),
+               kernel="voigt scatter-sum", avg_launch_ms=ms / launches,
+               busy_ms_per_launch=busy / launches, launches=launches,
+               samples_per_launch=samples / launches, flop_per_sample=flop_per_sample)
+    ka = res.get("kernel_alone")
+    if ka and ka["ms"] > 0:
+        a = ka["samples"] * flop_per_sample / (ka["ms"] / 1e3) / 1e12
+        out["kernel_alone"] = dict(achieved=a, frac=a / PEAK_VALU_TFLOPS,
+                                   avg_launch_ms=ka["ms"] / ka["launches"], launches=ka["launches"],
+                                   points=ka["points"], batch_points=ka["batch_points"],
+                                   note="same kernel with no other kernel beside it (one workspace slot), "
+                                        "stratified points, outside the timed region")
+    return out
 
 
 def cpu_baseline(w, seconds_budget, workers):

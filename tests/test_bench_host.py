@@ -1,0 +1,65 @@
+"""Host logic of bench.py (no GPU): roofline arithmetic on a synthetic result,
+the counter-summary lookup, the stratified sample and the one-GPU guard."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import bench
+from paper_2105_13611_amd import workload as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _result():
+    st = {k: dict(ms=0.0, busy_ms=0.0, launches=0) for k in ("point_state", "select", "scan", "emit", "odf")}
+    st["voigt"] = dict(ms=400.0, busy_ms=300.0, launches=4)
+    return dict(stage_ms=st, steps=2, stats=dict(voigt_samples=3.0e12),
+                kernel_alone=dict(ms=50.0, busy_ms=50.0, launches=2, samples=2.0e11, points=64, batch_points=16))
+
+
+def test_roofline_uses_the_union_of_launch_intervals():
+    r = bench.roofline(_result(), 10.0, "mixed")
+    # 2 steps x 3e12 samples x 10 FLOP over 0.3 s of busy time
+    assert abs(r["achieved"] - 6.0e13 / 0.3 / 1e12) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / bench.PEAK_VALU_TFLOPS) < 1e-12
+    assert r["avg_launch_ms"] == 100.0 and r["busy_ms_per_launch"] == 75.0
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s"
+    ka = r["kernel_alone"]
+    assert abs(ka["achieved"] - 2.0e11 * 10.0 / 0.05 / 1e12) < 1e-9
+    assert ka["avg_launch_ms"] == 25.0
+
+
+def test_peak_is_the_non_packed_valu_rate():
+    assert abs(bench.PEAK_VALU_TFLOPS - 78.6432) < 1e-9
+
+
+def test_traffic_summary_lookup():
+    for prec in ("mixed", "fp64"):
+        t = bench.traffic_per_launch(prec)
+        path = os.path.join(ROOT, "profiles", f"voigt{32 if prec == 'mixed' else 64}_full_table_hbm_traffic.md")
+        txt = open(path).read()
+        d = json.loads(txt[txt.index("```json") + 7: txt.index("```", txt.index("```json") + 7)])
+        if d["source_sha256"] == bench.kernel_sources_sha256():
+            assert t == d["hbm_bytes_per_launch"] and t > 0
+        else:
+            assert t is None
+
+
+def test_stratified_points_hold_the_corners():
+    pts = W.dfsynthe_tp_grid((2.0,))
+    idx = bench.stratified_points(pts, 16)
+    assert len(idx) == 16 and len(set(idx.tolist())) == 16
+    T, P = pts.T_K[idx], pts.log10_P[idx]
+    for t, p in [(T.min(), P.min()), (pts.T_K.min(), pts.log10_P.max()),
+                 (pts.T_K.max(), pts.log10_P.min()), (pts.T_K.max(), pts.log10_P.max())]:
+        assert np.any((np.isclose(T, t)) & (np.isclose(P, p)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
