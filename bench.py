@@ -173,8 +173,9 @@ def roofline(res, flop_per_sample, precision):
         out["kernel_alone"] = dict(achieved=a, frac=a / PEAK_VALU_TFLOPS,
                                    avg_launch_ms=ka["ms"] / ka["launches"], launches=ka["launches"],
                                    points=ka["points"], batch_points=ka["batch_points"],
-                                   note="same kernel with no other kernel beside it (one workspace slot), "
-                                        "stratified points, outside the timed region")
+                                   note="same kernel with no other kernel beside it (requests of one batch "
+                                        "each, so preparation, Voigt and reduction run in turn), stratified "
+                                        "points, outside the timed region")
     return out
 
 
