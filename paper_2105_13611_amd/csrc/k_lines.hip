@@ -167,7 +167,10 @@ struct LineEval {
 
 // Strength, damping, selection and window of one line at one point.  The
 // keep test S H(0,a) >= thr is skipped when S < thr already decides it
-// (H(0,a) = erfcx(a) <= 1 for a >= 0).
+// (H(0,a) = erfcx(a) <= 1 for a >= 0), and entirely when the caller already
+// knows the line is kept (kKept: the emission of survivors); the window is
+// computed the same way in both cases.
+template <bool kKept = false>
 __device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d,
                                               const PointState& ps, const TFactors& tf,
                                               const double* __restrict__ pop,
@@ -182,10 +185,10 @@ __device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d
   e.surv = false;
   e.jlo = 0;
   e.jhi = -1;
-  if (!(S >= thr)) return e;
+  if (!kKept && !(S >= thr)) return e;
   const double a = (d.g_rad + d.g_stark * ps.cS + d.g_vdw * ps.cW) / b;
   e.a = a;
-  if (!(S * erfcx(a) >= thr)) return e;
+  if (!kKept && !(S * erfcx(a) >= thr)) return e;
   const double xg = sqrt(fmax(0.0, log(2.0 * S / thr)));
   const double xl = sqrt(2.0 * S * a / (kSqrtPi * thr));
   const double xw = fmin(P.cap, fmax(xg, xl));
@@ -353,8 +356,8 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
     off += __popcll(m & below);
     const PointState ps = B.state[p];
     tf.update(d, ps.T);
-    const LineEval e = eval_line(P, d, ps, tf, B.pop + (int64_t)p * P.n_species * P.n_stages,
-                                 B.bT + (int64_t)p * P.n_species);
+    const LineEval e = eval_line<true>(P, d, ps, tf, B.pop + (int64_t)p * P.n_species * P.n_stages,
+                                       B.bT + (int64_t)p * P.n_species);
     const double Jd = rint(d.j0s);
     const int32_t J = (int32_t)Jd;
     const int64_t slot = (int64_t)p * B.rec_stride + off;

@@ -22,20 +22,22 @@ namespace {
 
 constexpr int kOdfThreads = 256;
 
+// Bitonic network over npow2 keys.  Each step of stage (k, j) is npow2/2
+// independent compare-exchanges of the pairs (i, i + j) with bit j of i
+// clear; a thread takes pairs by pair index, so no thread idles, and writes
+// min and max back without a branch (ascending where bit k of i is clear).
 template <typename K>
 __device__ void bitonic_sort(K* a, int npow2) {
+  const int half = npow2 >> 1;
   for (int k = 2; k <= npow2; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < npow2; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const K ai = a[i], aj = a[ixj];
-          const bool up = (i & k) == 0;
-          if ((ai > aj) == up) {
-            a[i] = aj;
-            a[ixj] = ai;
-          }
-        }
+      for (int q = threadIdx.x; q < half; q += blockDim.x) {
+        const int i = q + (q & ~(j - 1));   // insert a zero at bit j
+        const K ai = a[i], aj = a[i + j];
+        const K lo = ai < aj ? ai : aj, hi = ai < aj ? aj : ai;
+        const bool up = (i & k) == 0;
+        a[i] = up ? lo : hi;
+        a[i + j] = up ? hi : lo;
       }
       __syncthreads();
     }
