@@ -13,6 +13,8 @@ leg may import this package.  It shares no code with the HIP library; the
 only common input is the seeded workload generator, which holds no physics.
 """
 from .constants import *  # noqa: F401,F403
-from .physics import point_state, stage_fractions, populations, line_quantities  # noqa: F401
+from .physics import (point_state, stage_fractions, populations, line_quantities,  # noqa: F401
+                      ionisation_equilibrium, electron_density, saha_ratios)
 from .voigt import voigt_h  # noqa: F401
-from .odf import grid_size, grid_lambda_nm, fine_opacity, odf_reduce_bin, odf_point, odf  # noqa: F401
+from .odf import (grid_size, grid_lambda_nm, fine_opacity, odf_reduce_bin, odf_point, odf,  # noqa: F401
+                  fine_table_point)

@@ -13,6 +13,8 @@ M_ELECTRON = 9.1093837015e-28      # g
 AMU = 1.66053906660e-24            # g
 EV = 1.602176634e-12               # erg (exact)
 M_HYDROGEN_AMU = 1.008             # standard atomic weight of H
+CHI_HYDROGEN_EV = 13.598434599702  # ionisation energy of H I (NIST ASD)
+U_HYDROGEN = (2.0, 1.0)            # partition functions of H I (ground state) and H II
 
 #: pi e^2 / (m_e c): integrated cross-section per oscillator [cm^2 s^-1]
 PI_E2_MC = math.pi * E_CHARGE ** 2 / (M_ELECTRON * C_LIGHT)

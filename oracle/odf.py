@@ -14,6 +14,9 @@
   sorted point i covers [i, i+1) on the sorted axis and contributes to a
   sub-bin with the length of the overlap, so fractional sub-bin borders are
   honoured exactly.
+* Pre-tabulated high-resolution opacity (Sec. 4.1, option to pre-tabulate):
+  the table in ODF form with one sub-bin per fine point, i.e. the floored
+  opacity of every point of the grid.
 """
 import math
 
@@ -23,7 +26,7 @@ from .physics import grid_size, kappa_c, line_quantities
 from .voigt import voigt_h
 
 __all__ = ["grid_size", "grid_lambda_nm", "fine_opacity", "odf_reduce_bin",
-           "odf_point", "odf"]
+           "odf_point", "odf", "fine_table_point"]
 
 _CHUNK_SAMPLES = 4_000_000
 
@@ -115,6 +118,17 @@ def odf_point(lines, species, abundance, T, log10_P, vturb, layout, opts,
                     voigt_samples=int(np.sum(lq["jhi"][s] - lq["jlo"][s] + 1)))
     extra = dict(lq=lq, fine=fine)
     return steps, counters, extra
+
+
+def fine_table_point(lines, species, abundance, T, log10_P, vturb, layout, opts, j0=0, j1=None):
+    """Pre-tabulated opacity of one point on fine points [j0, j1): each fine
+    point is a bin of its own with a single sub-bin, whose mean is the
+    floored opacity max(kappa_l, cutoff kappa_c) of that point."""
+    lq = line_quantities(lines, species, abundance, T, log10_P, vturb, layout, opts)
+    j1 = lq["N"] if j1 is None else j1
+    kl = fine_opacity(lq, layout, j0, j1)
+    floor = opts.cutoff * kappa_c(grid_lambda_nm(layout, np.arange(j0, j1)), opts)
+    return np.maximum(kl, floor), lq
 
 
 def _odf_task(args):

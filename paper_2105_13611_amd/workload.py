@@ -110,6 +110,8 @@ class Options:
     kappa_c_ref: float = 1.0        # cm^2 / g at lambda_c_ref
     lambda_c_ref_nm: float = 500.0
     kappa_c_power: float = 3.0
+    output: str = "table"           # "table" (ODF) | "fine" (pre-tabulated opacity per fine point)
+    electrons: str = "fixed"        # "fixed" (P_e = pe_over_p P) | "equilibrium" (ionisation equilibrium)
 
 
 @dataclass

@@ -94,3 +94,30 @@ def test_duplicated_lines_double_opacity(cfg1):
     m = k1 > 0
     ratio = k2[m] / k1[m]
     assert np.median(ratio) == pytest.approx(2.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("mean", ["geometric", "arithmetic"])
+def test_fine_table_is_the_odf_of_one_point_bins(cfg1, mean):
+    # Sec. 4.1: the pre-tabulated opacity is an ODF whose bins are single
+    # fine points with one sub-bin
+    from dataclasses import replace
+    from paper_2105_13611_amd import workload as W
+    w = cfg1
+    N = oracle.grid_size(w.layout.lambda_first_nm, w.layout.lambda_last_nm, w.layout.resolving_power)
+    one = W.Layout(w.layout.lambda_first_nm, w.layout.lambda_last_nm, w.layout.resolving_power,
+                   np.arange(N + 1, dtype=np.int64), np.array([1.0]))
+    opts = replace(w.options, mean=mean)
+    fine, lq = oracle.fine_table_point(w.lines, w.species, w.species.abundance, 5000.0, 4.0, 2.0,
+                                       w.layout, opts)
+    assert fine.shape == (N,)
+    assert np.all(fine >= opts.cutoff * oracle.physics.kappa_c(oracle.grid_lambda_nm(w.layout, np.arange(N)), opts))
+    bins = np.unique(np.linspace(0, N - 1, 150).astype(np.int64))
+    steps, _, _ = oracle.odf_point(w.lines, w.species, w.species.abundance, 5000.0, 4.0, 2.0,
+                                   one, opts, bins=bins)
+    # (the ODF sums each bin's lines on their own: same terms, another order)
+    np.testing.assert_allclose(steps[:, 0], fine[bins], rtol=1e-13)
+    # a window of the grid is the same slice of the whole (up to the order
+    # in which the lines are summed)
+    part, _ = oracle.fine_table_point(w.lines, w.species, w.species.abundance, 5000.0, 4.0, 2.0,
+                                      w.layout, opts, 4000, 4100)
+    np.testing.assert_allclose(part, fine[4000:4100], rtol=1e-13)
