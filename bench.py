@@ -17,7 +17,12 @@ while the kernel sources still match it.
 The CPU baseline times the FP64 oracle on a bounded stratified sample of the
 same workload and scales it to points/s.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+--mode pretab times the pre-tabulated high-resolution opacity of a
+wavelength interval (one value per fine point) over the same T-P table and
+reports the T-P interpolation error of that opacity; --mode serve runs a
+request stream.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode table|pretab|serve]
 """
 import argparse
 import json
@@ -301,9 +306,128 @@ def run_serving(n_requests, rate_hz, workspace_gb, max_points, serve_config=4):
     return res
 
 
+PRETAB_METRIC = "pre-tabulated high-resolution opacity: (T,P) points/s"
+
+
+def _lattice(lt, lp):
+    """Points of a log10 T x log10 P lattice, P fastest."""
+    from paper_2105_13611_amd import workload as W
+    import numpy as np
+    TT, PP = np.meshgrid(10.0 ** np.asarray(lt), np.asarray(lp), indexing="ij")
+    return W.Points(TT.ravel(), PP.ravel(), np.full(TT.size, 2.0))
+
+
+def interpolation_study(plan, w, T_range=(4000.0, 12000.0), P_range=(0.0, 6.0), refine=(1, 2)):
+    """T-P interpolation error of the pre-tabulated opacity (Sec. 4.1; the
+    T-P grid of Sec. 4.2).  A lattice with the DFSYNTHE steps (log10 T by
+    2/56, log10 P by 0.5), and the same refined, over a sub-range of the
+    table: the opacity computed at the centre of every cell against the
+    bilinear interpolation in (log T, log P) of log kappa from its four
+    corners, over every fine point."""
+    import numpy as np
+    import torch
+    out = {}
+    for r in refine:
+        dT, dP = (2.0 / 56.0) / r, 0.5 / r
+        k0 = math.floor(math.log10(T_range[0] / 2000.0) / (2.0 / 56.0))
+        lt = math.log10(2000.0) + k0 * (2.0 / 56.0) + dT * np.arange(
+            int(math.ceil((math.log10(T_range[1]) - math.log10(2000.0) - k0 * 2.0 / 56.0) / dT)) + 1)
+        lp = P_range[0] + dP * np.arange(int(round((P_range[1] - P_range[0]) / dP)) + 1)
+        nodes = _lattice(lt, lp)
+        cent = _lattice(0.5 * (lt[:-1] + lt[1:]), 0.5 * (lp[:-1] + lp[1:]))
+        t0 = time.perf_counter()
+        kn, _ = plan.compute(w.species.abundance, nodes)
+        kc, _ = plan.compute(w.species.abundance, cent)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ln = kn.double().log().view(lt.size, lp.size, -1)
+        li = 0.25 * (ln[:-1, :-1] + ln[1:, :-1] + ln[:-1, 1:] + ln[1:, 1:])
+        err = (li.reshape(kc.shape) - kc.double().log()).exp().sub(1.0).abs()
+        sub = err[:, ::16].flatten().cpu().numpy()
+        out[f"step_1/{r}"] = dict(
+            log10_T_step=dT, log10_P_step=dP, nodes=nodes.n_points, centres=cent.n_points,
+            median=float(np.median(sub)), p99=float(np.percentile(sub, 99.0)),
+            max=float(err.max().item()), frac_above_1pct=float((err > 0.01).double().mean().item()),
+            frac_above_3pct=float((err > 0.03).double().mean().item()), seconds=dt)
+        log(f"[bench] interpolation at 1/{r} of the DFSYNTHE steps: {out[f'step_1/{r}']}")
+        del kn, kc, ln, li, err
+        torch.cuda.empty_cache()
+    out["T_range_K"] = list(T_range)
+    out["log10_P_range"] = list(P_range)
+    out["note"] = ("relative error of exp(bilinear interpolation of ln kappa in (log T, log P)) at cell "
+                   "centres against the computed floored opacity; median and p99 over every 16th fine "
+                   "point, max and fractions over all")
+    return out
+
+
+def run_pretab(args):
+    """Pre-tabulated high-resolution opacity (Sec. 4.1): the floored line
+    opacity of every fine point of a wavelength interval at R = 5e5, over
+    the DFSYNTHE T-P table, and the T-P interpolation study."""
+    import numpy as np
+    import torch
+    from dataclasses import replace
+    from paper_2105_13611_amd import odf
+    from paper_2105_13611_amd import workload as W
+    lo, hi = args.pretab_nm
+    # the full list's line density (1e7 lines log-uniform over 9 nm - 10 um)
+    n_lines = int(round(1e7 * math.log(hi / lo) / math.log(W.LAMBDA_LAST_FULL_NM / 9.0)))
+    w = W.config(2, n_lines=n_lines, lam_range=(lo, hi), n_bins=1)
+    w = replace(w, options=replace(w.options, output="fine"))
+    N = W.grid_size(lo, hi, W.RESOLVING_POWER)
+    prec = "mixed" if args.precision == "both" else args.precision
+    log(f"[bench] pretab: {n_lines} lines in {lo}-{hi} nm, N = {N}, {w.points.n_points} points, {prec}")
+    plan = odf.plan_for(w, precision=prec, workspace_bytes=int(args.workspace_gb * (1 << 30)),
+                        kernel_timing=True)
+    out = plan.new_out(w.points.n_points)
+    for k in range(args.warmup):
+        plan.compute(w.species.abundance, w.points, out)
+    plan.stage_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for k in range(args.steps):
+        _, stats = plan.compute(w.species.abundance, w.points, out)
+        log(f"[bench] pretab: step {k + 1}/{args.steps} done at {time.perf_counter() - t0:.2f} s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    times = plan.stage_times(reset=True)
+    value = w.points.n_points * args.steps / dt
+    fine = times["odf"]
+    # the fine-output kernel: one read and one write per fine point
+    bytes_per_launch = (8 if prec == "fp64" else 4) * 2 * N * w.points.n_points * args.steps / max(fine["launches"], 1)
+    res = {
+        "metric": PRETAB_METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"pre-tabulated opacity {lo}-{hi} nm at R=5e5 ({N} fine points), "
+                               f"{n_lines} synthetic lines (the 1e7-line list's density), "
+                               f"57 T x 25 log P at vturb 2 km/s",
+                   "points": w.points.n_points, "lines": n_lines, "grid_points": N},
+        "fine_points_per_s": value * N,
+        "voigt_samples_per_s": stats["voigt_samples"] * args.steps / dt,
+        "stage_ms": {k: v["ms"] for k, v in times.items()},
+        "stage_busy_ms": {k: v["busy_ms"] for k, v in times.items()},
+        "fine_output_kernel": dict(launches=fine["launches"], avg_launch_ms=fine["ms"] / max(fine["launches"], 1),
+                                   achieved_GBs=bytes_per_launch / (fine["ms"] / max(fine["launches"], 1)) / 1e6,
+                                   peak_GBs=8000.0),
+        "checksum": float(out.double().sum().item()),
+    }
+    del out
+    torch.cuda.empty_cache()
+    if not args.no_interp:
+        res["interpolation"] = interpolation_study(plan, w)
+    plan.destroy()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["table", "serve"], default="table")
+    ap.add_argument("--mode", choices=["table", "serve", "pretab"], default="table")
+    ap.add_argument("--pretab-nm", type=float, nargs=2, default=[300.0, 450.0],
+                    help="wavelength interval of --mode pretab (nm)")
+    ap.add_argument("--no-interp", action="store_true", help="--mode pretab without the interpolation study")
     ap.add_argument("--serve-requests", type=int, default=12)
     ap.add_argument("--serve-rate", type=float, default=0.0, help="req/s (0 = the stream's 20 req/s)")
     ap.add_argument("--serve-max-points", type=int, default=0)
@@ -339,6 +463,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: 3 copies of {args.copy_calibration_mb} MiB")
         del a, b
+    if args.mode == "pretab":
+        print(json.dumps(run_pretab(args)), flush=True)
+        return
     if args.mode == "serve":
         print(json.dumps(run_serving(args.serve_requests, args.serve_rate, args.workspace_gb,
                                      args.serve_max_points, args.serve_config)), flush=True)

@@ -55,6 +55,26 @@ typedef enum {
   ODF_MEAN_ARITHMETIC = 1  /* 'odf mean arithmetic' (App. G, module-I keywords) */
 } odf_mean;
 
+/* What odf_compute and the request loop write per point. */
+typedef enum {
+  ODF_OUT_TABLE = 0,  /* the ODF table: [n_bins][n_steps] sub-bin means */
+  ODF_OUT_FINE = 1    /* pre-tabulated high-resolution opacity (Sec. 4.1, option to
+                         pre-tabulate): the floored line opacity of every fine
+                         point, [N] values, i.e. an ODF whose bins are single
+                         fine points with one sub-bin; bins and sub-bins of the
+                         layout are not used */
+} odf_output;
+
+/* How the electron density of a point is found. */
+typedef enum {
+  ODF_NE_FIXED = 0,       /* P_e = pe_over_p * P */
+  ODF_NE_EQUILIBRIUM = 1  /* ionisation equilibrium of hydrogen and every species of
+                             the table (App. A, without molecules): Newton-Raphson
+                             on the neutral densities and n_e under particle and
+                             charge conservation, until every relative change is
+                             below 1e-4 */
+} odf_electrons;
+
 typedef enum { ODF_PENDING = 0, ODF_RUNNING = 1, ODF_DONE = 2, ODF_FAILED = 3 } odf_state;
 
 /* Line list, structure of arrays, any order (host).  The plan sorts a copy
@@ -106,7 +126,8 @@ typedef struct {
  *                     its window ends where its envelope drops below that
  *                     level; the fine-grid opacity is floored at it.
  *   window_cap_doppler cap of the half-window in Doppler widths.
- *   pe_over_p         electron pressure as a fraction of the gas pressure.
+ *   pe_over_p         electron pressure as a fraction of the gas pressure
+ *                     (electrons = ODF_NE_FIXED; ignored otherwise).
  *   kappa_c_*         continuum kappa_c(lambda) = ref * (lambda/lambda_ref)^power [cm^2/g].
  *   workspace         caller-owned device memory used for all intermediate
  *                     data; must outlive the plan.  Its size bounds the number
@@ -117,7 +138,13 @@ typedef struct {
  *   loop_streams      streams used by the request loop (0 = 2).
  *   kernel_timing     nonzero: odf_compute brackets every kernel launch with
  *                     HIP events on options.stream; totals are read with
- *                     odf_stage_times(). */
+ *                     odf_stage_times().
+ *   output            odf_output: ODF table (default) or fine-grid opacity.
+ *   electrons         odf_electrons: fixed P_e / P (default) or the
+ *                     ionisation equilibrium.  With the equilibrium, a point
+ *                     whose Newton iteration does not converge within 100
+ *                     steps fails its request (odf_compute returns
+ *                     ODF_E_INTERNAL naming the point; a ticket ends FAILED). */
 typedef struct {
   odf_precision precision;
   odf_mean mean;
@@ -131,6 +158,8 @@ typedef struct {
   int32_t max_batch_points;
   int32_t loop_streams;
   int32_t kernel_timing;
+  int32_t output;
+  int32_t electrons;
 } odf_options;
 
 /* One ODF request.
@@ -138,8 +167,9 @@ typedef struct {
  *   T_K, log10_P_cgs, vturb_kms  host [n_points] point list (a T-P grid and a
  *              list of microturbulences, App. G 'velocities values' and the
  *              odf.tpgrid file, expanded by the caller)
- *   out        device buffer [n_points][n_bins][n_steps] of double (FP64) or
- *              float (MIXED), caller-owned, written in full; valid once
+ *   out        device buffer [n_points][n_bins][n_steps] (ODF_OUT_TABLE) or
+ *              [n_points][N] (ODF_OUT_FINE) of double (FP64) or float
+ *              (MIXED), caller-owned, written in full; valid once
  *              odf_compute returns or odf_poll reports ODF_DONE. */
 typedef struct {
   const double *abundance;
@@ -221,6 +251,14 @@ odf_status odf_stage_lines(odf_plan_t *plan, const odf_request *req, int32_t poi
                            int64_t *n_surv, int64_t *voigt_samples,
                            int64_t *orig_index, int32_t *j_lo, int32_t *j_hi,
                            double *S, double *a, double *b);
+
+/* Gas state of point `point` of req (Sec. 2.1; App. A): state host [4]
+ * receives n_e, the heavy-particle density N_heavy = P/kT - n_e (with fixed
+ * P_e: (P - P_e)/kT), the hydrogen density N_H [cm^-3] and the mass density
+ * rho [g cm^-3]; *iterations the Newton steps of the ionisation equilibrium
+ * (0 with fixed P_e, negative if it did not converge). */
+odf_status odf_stage_state(odf_plan_t *plan, const odf_request *req, int32_t point,
+                           double *state, int32_t *iterations);
 
 /* Line opacity on the fine grid for point `point` (before the floor):
  * kappa_dev is a device buffer of N doubles (FP64 plan) or floats (MIXED). */

@@ -3,8 +3,9 @@
 //
 // Physics (Witzke et al. 2021):
 //  - Saha-Boltzmann stage populations N_k/U_k per gram with the electron
-//    density fixed by P_e = pe_over_p * P (Sec. 2.1; App. A; App. E first
-//    stage item i).
+//    density fixed by P_e = pe_over_p * P or taken from the ionisation
+//    equilibrium of hydrogen and every species (Sec. 2.1; App. A; App. E
+//    first stage item i).
 //  - Doppler width dnu_D = (nu0/c) sqrt(2kT/m + v_turb^2) (App. E).
 //  - Line strength S of ell_nu = S H(x, a) from eq. l_nu_line (Sec. 2.1),
 //    damping parameter a = gamma / (4 pi dnu_D).
@@ -60,16 +61,206 @@ hipError_t launch_prep_lines(hipStream_t st, int64_t n, const double* lam_nm, co
   return hipGetLastError();
 }
 
-// One workgroup per point: gas state, Saha stage fractions (log space),
-// populations N_k/(U_k rho) and the thermal-plus-turbulent b = dnu_D/nu0.
+// ---- ionisation equilibrium (App. A, without molecules) --------------------
+//
+// Elements: hydrogen (two stages) and every species of the table.  With the
+// Saha ratios phi_k = n_{k+1} n_e / n_k, R_k = phi_0 ... phi_{k-1}, an
+// element of neutral density n holds N = n G nuclei and gives n Q
+// electrons, G = sum_k R_k n_e^-k, Q = sum_k k R_k n_e^-k.  Unknowns: the
+// neutral densities and n_e; equations: particles (sum N + n_e = P/kT),
+// abundances (N_s = A_s N_H) and charge (sum n Q = n_e).  Each Newton step
+// solves J d = f.  J has nonzeros only in the hydrogen column, the n_e
+// column, the particle row and the charge row, so eliminating every
+// species' own unknown leaves a 2x2 system in (d_H, d_e): O(S) work per
+// step, one species per lane, with wave sums.  The step is scaled by the
+// largest lam <= 1 that keeps every unknown within a factor of 10 of its
+// value; the iteration stops when every relative change is below 1e-4.
+// Start: n_e = min(sqrt(P/kT sum nu_i phi_0,i), P/2kT) (weak ionisation,
+// capped at fully ionised hydrogen), neutral densities consistent with it.
+constexpr double kChiH = 13.598434599702;   // eV, H I
+constexpr double kU_HI = 2.0, kU_HII = 1.0;
+constexpr int kNeMaxIter = 100;
+constexpr double kNeTol = 1e-4;
+
+// Butterfly reductions over the 64 lanes: every lane ends with the same
+// bits (each step adds the same two values in both lanes).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// G, Q and their n_e derivatives from the Saha ratios phi[0..K-2].
+struct ElemGQ {
+  double G, Q, dG, dQ;
+};
+__device__ __forceinline__ ElemGQ elem_gq(const double* phi, int K, double inv_ne) {
+  ElemGQ e{1.0, 0.0, 0.0, 0.0};
+  double R = 1.0, q2 = 0.0;
+  double pk = 1.0;
+  for (int k = 1; k < K; ++k) {
+    R *= phi[k - 1];
+    pk *= inv_ne;
+    const double t = R * pk;
+    e.G += t;
+    e.Q += k * t;
+    q2 += (double)(k * k) * t;
+  }
+  e.dG = -e.Q * inv_ne;
+  e.dQ = -q2 * inv_ne;
+  return e;
+}
+
+// Step bound of one unknown: x - lam d stays within [x/10, 10 x].
+__device__ __forceinline__ double step_bound(double x, double d) {
+  if (d > 0.0) return 0.9 * x / d;
+  if (d < 0.0) return 9.0 * x / -d;
+  return 1.0;
+}
+
+// Solves for n_e with the whole wave (blockDim.x == 64).  The neutral
+// density of species s and its Saha ratios live in the point's population
+// row (pop[s K] and pop[s K + 1 ..]) until the populations overwrite them.
+// Returns n_e; *iters receives the step count (negative: no convergence).
+__device__ double equilibrium_ne(const Params& P, const Batch& B, int p, double T, double n_tot,
+                                 double saha, int* iters) {
+  const int S = P.n_species, K = P.n_stages;
+  const int lane = threadIdx.x;
+  const double kT = kK * T;
+  double* row = B.pop + (int64_t)p * S * K;
+  const double* A = B.abundance;
+  // hydrogen: one ratio
+  const double phiH = 2.0 * (kU_HII / kU_HI) * saha * pow(T, 1.5) * exp(-kChiH * kEv / kT);
+  // species ratios and the start
+  double part = 0.0, asum = 0.0;
+  for (int s = lane; s < S; s += 64) {
+    double* r = row + s * K;
+    for (int k = 0; k + 1 < K; ++k)
+      r[1 + k] = 2.0 * (P.part_fn[s * K + k + 1] / P.part_fn[s * K + k]) * saha * pow(T, 1.5) *
+                 exp(-P.chi_ev[s * (K - 1) + k] * kEv / kT);
+    part += A[s] * (K > 1 ? r[1] : 0.0);
+    asum += A[s];
+  }
+  const double Atot = 1.0 + wave_sum(asum);
+  const double nuphi = (phiH + wave_sum(part)) / Atot;
+  double ne = fmin(sqrt(n_tot * nuphi), 0.5 * n_tot);
+  double nH;
+  {
+    const double inv = 1.0 / ne;
+    nH = (n_tot - ne) / (Atot * elem_gq(&phiH, 2, inv).G);
+    for (int s = lane; s < S; s += 64) {
+      double* r = row + s * K;
+      r[0] = A[s] * (n_tot - ne) / (Atot * elem_gq(r + 1, K, inv).G);
+    }
+  }
+  int it = 0;
+  bool done = false;
+  while (it < kNeMaxIter && !done) {
+    ++it;
+    const double inv = 1.0 / ne;
+    const ElemGQ h = elem_gq(&phiH, 2, inv);
+    // species sums
+    double sNG = 0.0, sNdG = 0.0, sNQ = 0.0, sNdQ = 0.0, sF = 0.0, sC = 0.0, sQAG = 0.0,
+           sQC = 0.0, sQF = 0.0;
+    for (int s = lane; s < S; s += 64) {
+      const double* r = row + s * K;
+      const double n = r[0];
+      const ElemGQ e = elem_gq(r + 1, K, inv);
+      const double fs = n * e.G - A[s] * nH * h.G;
+      const double cs = n * e.dG - A[s] * nH * h.dG;
+      sNG += n * e.G;
+      sNdG += n * e.dG;
+      sNQ += n * e.Q;
+      sNdQ += n * e.dQ;
+      sF += fs;
+      sC += cs;
+      sQAG += e.Q * A[s] * h.G / e.G;
+      sQC += e.Q * cs / e.G;
+      sQF += e.Q * fs / e.G;
+    }
+    sNG = wave_sum(sNG);
+    sNdG = wave_sum(sNdG);
+    sNQ = wave_sum(sNQ);
+    sNdQ = wave_sum(sNdQ);
+    sF = wave_sum(sF);
+    sC = wave_sum(sC);
+    sQAG = wave_sum(sQAG);
+    sQC = wave_sum(sQC);
+    sQF = wave_sum(sQF);
+    // residuals and the reduced 2x2 system in (d_H, d_e)
+    const double f0 = nH * h.G + sNG + ne - n_tot;
+    const double fe = nH * h.Q + sNQ - ne;
+    const double a11 = h.G * Atot;
+    const double a12 = (nH * h.dG + sNdG + 1.0) - sC;
+    const double b1 = f0 - sF;
+    const double a21 = h.Q + sQAG;
+    const double a22 = (nH * h.dQ + sNdQ - 1.0) - sQC;
+    const double b2 = fe - sQF;
+    const double det = a11 * a22 - a12 * a21;
+    const double dH = (b1 * a22 - a12 * b2) / det;
+    const double de = (a11 * b2 - a21 * b1) / det;
+    // step bound over every unknown
+    double lam = fmin(1.0, fmin(step_bound(nH, dH), step_bound(ne, de)));
+    for (int s = lane; s < S; s += 64) {
+      const double* r = row + s * K;
+      const double n = r[0];
+      const ElemGQ e = elem_gq(r + 1, K, inv);
+      const double fs = n * e.G - A[s] * nH * h.G;
+      const double cs = n * e.dG - A[s] * nH * h.dG;
+      const double ds = (fs + A[s] * h.G * dH - cs * de) / e.G;
+      lam = fmin(lam, step_bound(n, ds));
+    }
+    lam = wave_min(lam);
+    // update and the largest relative change
+    double rel = 0.0;
+    for (int s = lane; s < S; s += 64) {
+      double* r = row + s * K;
+      const double n = r[0];
+      const ElemGQ e = elem_gq(r + 1, K, inv);
+      const double fs = n * e.G - A[s] * nH * h.G;
+      const double cs = n * e.dG - A[s] * nH * h.dG;
+      const double ds = (fs + A[s] * h.G * dH - cs * de) / e.G;
+      const double nn = n - lam * ds;
+      rel = fmax(rel, fabs(lam * ds) / nn);
+      r[0] = nn;
+    }
+    const double nH1 = nH - lam * dH, ne1 = ne - lam * de;
+    rel = fmax(rel, fmax(fabs(lam * dH) / nH1, fabs(lam * de) / ne1));
+    rel = wave_max(rel);
+    nH = nH1;
+    ne = ne1;
+    done = rel < kNeTol;
+  }
+  *iters = done ? it : -it;
+  return ne;
+}
+
+// One workgroup (one wave) per point: gas state, Saha stage fractions (log
+// space), populations N_k/(U_k rho) and the thermal-plus-turbulent
+// b = dnu_D/nu0.
 __global__ void k_point_state(Params P, Batch B) {
   const int p = blockIdx.x;
   const double T = B.T[p];
   const double Pg = exp10(B.log10P[p]);
   const double kT = kK * T;
-  const double pe = P.pe_over_p * Pg;
-  const double n_e = pe / kT;
-  const double n_heavy = (Pg - pe) / kT;
+  const double saha = pow(2.0 * kPi * kMe * kK / (kH * kH), 1.5);
+  double n_e, n_heavy;
+  int iters = 0;
+  if (P.electrons == 1) {
+    n_e = equilibrium_ne(P, B, p, T, Pg / kT, saha, &iters);
+    n_heavy = Pg / kT - n_e;
+  } else {
+    const double pe = P.pe_over_p * Pg;
+    n_e = pe / kT;
+    n_heavy = (Pg - pe) / kT;
+  }
   const int S = P.n_species, K = P.n_stages;
   // sums over species in a fixed order (thread-independent, deterministic)
   double sumA = 0.0, sumAM = 0.0;
@@ -93,8 +284,8 @@ __global__ void k_point_state(Params P, Batch B) {
     B.state[p] = ps;
     B.hmax[p] = 0;
     B.nsamp[p] = 0ull;
+    B.nit[p] = iters;
   }
-  const double saha = pow(2.0 * kPi * kMe * kK / (kH * kH), 1.5);
   const double vt = B.vt_kms[p] * 1e5;
   for (int s = threadIdx.x; s < S; s += blockDim.x) {
     double logf[8];

@@ -14,6 +14,8 @@
 // they are bitonic-sorted in LDS, padded with all-ones keys to a power of
 // two.  Bins too large for LDS sort in a global scratch slab with the same
 // network.  Step sums are FP64 in a fixed reduction order.
+#include <algorithm>
+
 #include "odf_internal.h"
 
 namespace odf {
@@ -123,7 +125,42 @@ __global__ __launch_bounds__(kOdfThreads) void k_odf(Params P, const T* __restri
   }
 }
 
+// Pre-tabulated high-resolution opacity (Sec. 4.1): every fine point is a
+// bin of its own with one sub-bin, whose mean is the floored value itself.
+// The floor is taken exactly as in k_odf, so the result equals, bit for bit,
+// the arithmetic-mean ODF of one-point bins.  Memory-bound: one read and one
+// write per fine point, coalesced, one point of the batch per grid row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fine(Params P, const T* __restrict__ kappa,
+                                              int64_t kappa_stride, T* __restrict__ out) {
+  const int p = blockIdx.y;
+  const T* kp = kappa + (int64_t)p * kappa_stride;
+  T* op = out + (int64_t)p * P.N;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < P.N;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const double lam = P.lambda_first_nm * exp((double)j * P.lnq);
+    const double fl = P.cutoff * (P.kc_ref * pow(lam / P.kc_lref, P.kc_power));
+    const T v = kp[j];
+    const T f = (T)fl;
+    op[j] = v > f ? v : f;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fine(hipStream_t st, const Params& P, const void* kappa, int64_t kappa_stride,
+                       int32_t n_points, void* out) {
+  if (n_points == 0 || P.N == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((P.N + 255) / 256, 2048);
+  dim3 grid((unsigned)blocks, n_points);
+  if (P.precision == 1)
+    hipLaunchKernelGGL(k_fine<float>, grid, dim3(256), 0, st, P, (const float*)kappa, kappa_stride,
+                       (float*)out);
+  else
+    hipLaunchKernelGGL(k_fine<double>, grid, dim3(256), 0, st, P, (const double*)kappa,
+                       kappa_stride, (double*)out);
+  return hipGetLastError();
+}
 
 hipError_t launch_odf(hipStream_t st, const Params& P, const void* kappa, int64_t kappa_stride,
                       int32_t n_points, void* out, const OdfClasses& C, void* gscratch,

@@ -43,6 +43,7 @@ RequestLoop::~RequestLoop() {
     if (s.h_pts) (void)hipHostFree(s.h_pts);
     if (s.h_nsurv) (void)hipHostFree(s.h_nsurv);
     if (s.h_nsamp) (void)hipHostFree(s.h_nsamp);
+    if (s.h_nit) (void)hipHostFree(s.h_nit);
   }
   for (auto st : streams_) (void)hipStreamDestroy(st);
 }
@@ -67,7 +68,8 @@ bool RequestLoop::start_locked() {
     if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void**)&s.h_pts, sizeof(double) * (3 * P + S), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&s.h_nsurv, sizeof(int32_t) * P, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&s.h_nsamp, sizeof(unsigned long long) * P, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&s.h_nsamp, sizeof(unsigned long long) * P, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&s.h_nit, sizeof(int32_t) * P, hipHostMallocDefault) != hipSuccess) {
       set_error("request loop: event or pinned-buffer allocation failed");
       start_failed_ = true;
       return false;
@@ -194,13 +196,13 @@ void RequestLoop::dispatch_locked(Slot& s, const std::shared_ptr<Request>& r) {
   Batch B{};
   if (st == ODF_OK) {
     B = make_batch(plan_, layout_, s.base, n);
-    const size_t osz = plan_->opts.precision == ODF_PREC_MIXED ? 4 : 8;
-    char* outp = static_cast<char*>(r->out) + (size_t)first * plan_->n_bins * plan_->n_steps * osz;
+    char* outp = static_cast<char*>(r->out) + (size_t)first * out_point_bytes(plan_);
     st = enqueue_batch(plan_, B, s.base, layout_, outp, s.stream);
   }
   if (st == ODF_OK) {
     if ((e = hipMemcpyAsync(s.h_nsurv, B.nsurv, 4 * n, hipMemcpyDeviceToHost, s.stream)) != hipSuccess ||
         (e = hipMemcpyAsync(s.h_nsamp, B.nsamp, 8 * n, hipMemcpyDeviceToHost, s.stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(s.h_nit, B.nit, 4 * n, hipMemcpyDeviceToHost, s.stream)) != hipSuccess ||
         (e = hipEventRecord(s.done, s.stream)) != hipSuccess) {
       set_error("request loop read-back failed: %s", hipGetErrorString(e));
       st = ODF_E_DEVICE;
@@ -253,7 +255,17 @@ void RequestLoop::run() {
       if (!s.busy) continue;
       const hipError_t q = hipEventQuery(s.done);
       if (q == hipSuccess) {
-        finish_locked(s, true, "");
+        int bad = -1;
+        for (int i = 0; i < s.count && bad < 0; ++i)
+          if (s.h_nit[i] < 0) bad = i;
+        if (bad < 0) {
+          finish_locked(s, true, "");
+        } else {
+          char msg[128];
+          std::snprintf(msg, sizeof msg, "ionisation equilibrium did not converge at point %d",
+                        s.first + bad);
+          finish_locked(s, false, msg);
+        }
         progress = true;
       } else if (q != hipErrorNotReady) {
         finish_locked(s, false, hipGetErrorString(q));

@@ -25,6 +25,8 @@ odf_status enqueue_sum(odf_plan_s* p, const Batch& B, char* slot_base, const Slo
 odf_status enqueue_batch(odf_plan_s* p, const Batch& B, char* slot_base, const SlotLayout& s,
                          void* out, hipStream_t st, StageTimer* timer = nullptr);
 odf_status validate_request(const odf_plan_s* p, const odf_request* r, bool need_out);
+// Bytes of one point's output (ODF table or fine-grid opacity).
+size_t out_point_bytes(const odf_plan_s* p);
 
 struct Request {
   int64_t id = 0;
@@ -46,6 +48,7 @@ struct Slot {
   double* h_pts = nullptr;             // pinned staging: T, logP, vt, abundance
   int32_t* h_nsurv = nullptr;          // pinned read-back
   unsigned long long* h_nsamp = nullptr;
+  int32_t* h_nit = nullptr;            // ionisation-equilibrium steps per point
   std::shared_ptr<Request> req;
   int32_t first = 0, count = 0;
   bool busy = false;

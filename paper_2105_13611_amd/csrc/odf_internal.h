@@ -151,6 +151,7 @@ struct Batch {
   int32_t* nsurv;       // [B]
   int32_t* hmax;        // [B]         max half-window in fine points
   unsigned long long* nsamp;  // [B]
+  int32_t* nit;         // [B]         ionisation-equilibrium steps (0: fixed P_e; < 0: not converged)
   void* rec;            // [B][L] Rec32 or Rec64
   int2* win;            // [B][L] (jlo, jhi) of each record, scanned by the Voigt kernels
   void* kappa;          // [B][N] float or double
@@ -174,6 +175,8 @@ struct Params {
   const double* Fcum;      // device [n_steps+1] cumulative fractions, F[0]=0, F[n]=1
   int32_t mean;            // 0 geometric, 1 arithmetic
   int32_t precision;       // 0 fp64, 1 mixed
+  int32_t output;          // 0 ODF table, 1 fine-grid opacity
+  int32_t electrons;       // 0 fixed P_e / P, 1 ionisation equilibrium
 };
 
 // ---- launchers (defined in the .hip files) ---------------------------------
@@ -189,6 +192,10 @@ hipError_t launch_select(hipStream_t st, const Params& P, const DevLines& L, con
 hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const Batch& B);
 hipError_t launch_emit(hipStream_t st, const Params& P, const DevLines& L, const Batch& B, int rec64);
 hipError_t launch_voigt(hipStream_t st, const Params& P, const Batch& B, const QuadConsts* Q);
+// Floored fine-grid opacity of n_points grids (kappa rows kappa_stride apart)
+// into out [n_points][N].
+hipError_t launch_fine(hipStream_t st, const Params& P, const void* kappa, int64_t kappa_stride,
+                       int32_t n_points, void* out);
 // Bins grouped by padded size (power of two) so each ODF launch reserves only
 // the LDS its largest bin needs.  bins: device list of bin indices, class c at
 // [offset[c], offset[c] + count[c]).

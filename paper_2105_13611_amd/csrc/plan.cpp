@@ -180,7 +180,12 @@ odf_status validate_options(const odf_options* o) {
     set_error("options: window_cap_doppler must be in (0, 2000]");
     return ODF_E_INVALID;
   }
-  if (!(o->pe_over_p > 0.0 && o->pe_over_p < 1.0)) { set_error("options: pe_over_p must be in (0, 1)"); return ODF_E_INVALID; }
+  if (o->output != ODF_OUT_TABLE && o->output != ODF_OUT_FINE) { set_error("options: bad output"); return ODF_E_INVALID; }
+  if (o->electrons != ODF_NE_FIXED && o->electrons != ODF_NE_EQUILIBRIUM) { set_error("options: bad electrons"); return ODF_E_INVALID; }
+  if (o->electrons == ODF_NE_FIXED && !(o->pe_over_p > 0.0 && o->pe_over_p < 1.0)) {
+    set_error("options: pe_over_p must be in (0, 1)");
+    return ODF_E_INVALID;
+  }
   if (!finite_pos(o->kappa_c_ref) || !finite_pos(o->lambda_c_ref_nm) || !std::isfinite(o->kappa_c_power)) {
     set_error("options: continuum parameters must be finite, reference values > 0");
     return ODF_E_INVALID;
@@ -215,6 +220,7 @@ SlotLayout make_slot(const odf_plan_s* p, int32_t pts) {
   s.off_nsurv = take(4 * pts);
   s.off_hmax = take(4 * pts);
   s.off_nsamp = take(8 * pts);
+  s.off_nit = take(4 * pts);
   s.off_rec = take((mixed ? (int64_t)sizeof(Rec32) : (int64_t)sizeof(Rec64)) * std::max<int64_t>(L, 1) * pts);
   s.off_win = take((int64_t)sizeof(int2) * std::max<int64_t>(L, 1) * pts);
   s.off_kappa = take((mixed ? 4 : 8) * p->N * pts);
@@ -239,6 +245,7 @@ Batch make_batch(const odf_plan_s* p, const SlotLayout& s, char* base, int32_t n
   B.nsurv = reinterpret_cast<int32_t*>(base + s.off_nsurv);
   B.hmax = reinterpret_cast<int32_t*>(base + s.off_hmax);
   B.nsamp = reinterpret_cast<unsigned long long*>(base + s.off_nsamp);
+  B.nit = reinterpret_cast<int32_t*>(base + s.off_nit);
   B.rec = base + s.off_rec;
   B.win = reinterpret_cast<int2*>(base + s.off_win);
   B.kappa = base + s.off_kappa;
@@ -289,10 +296,19 @@ odf_status enqueue_sum(odf_plan_s* p, const Batch& B, char* slot_base, const Slo
   { TimedLaunch tl(timer, st, 4); HIP_TRY(launch_voigt(st, p->params, B, p->d_quad)); }
   if (out) {
     TimedLaunch tl(timer, st, 5);
-    HIP_TRY(launch_odf(st, p->params, B.kappa, B.kappa_stride, B.n_points, out, p->odf_classes,
-                       slot_base + s.off_gscr, p->d_goff, p->gscr_elems));
+    if (p->params.output == 1)
+      HIP_TRY(launch_fine(st, p->params, B.kappa, B.kappa_stride, B.n_points, out));
+    else
+      HIP_TRY(launch_odf(st, p->params, B.kappa, B.kappa_stride, B.n_points, out, p->odf_classes,
+                         slot_base + s.off_gscr, p->d_goff, p->gscr_elems));
   }
   return ODF_OK;
+}
+
+size_t out_point_bytes(const odf_plan_s* p) {
+  const size_t osz = p->opts.precision == ODF_PREC_MIXED ? 4 : 8;
+  const size_t n = p->opts.output == ODF_OUT_FINE ? (size_t)p->N : (size_t)p->n_bins * p->n_steps;
+  return n * osz;
 }
 
 odf_status enqueue_batch(odf_plan_s* p, const Batch& B, char* slot_base, const SlotLayout& s,
@@ -566,6 +582,8 @@ odf_status odf_plan(const odf_lines* lines, const odf_species* species, const od
     P.Fcum = Fc;
     P.mean = p->opts.mean == ODF_MEAN_ARITHMETIC ? 1 : 0;
     P.precision = p->opts.precision == ODF_PREC_MIXED ? 1 : 0;
+    P.output = p->opts.output == ODF_OUT_FINE ? 1 : 0;
+    P.electrons = p->opts.electrons == ODF_NE_EQUILIBRIUM ? 1 : 0;
   }
   p->quad = make_quad_consts();
   {
@@ -686,7 +704,7 @@ odf_status odf_compute(odf_plan_t* p, const odf_request* r, odf_stats* stats) {
   const int n = r->n_points;
   const int S = p->n_species;
   // pinned host staging: point arrays and abundances in, counters out
-  const size_t need = (size_t)8 * (3 * (size_t)n + S) + 12 * (size_t)std::max(n, 1) + 64;
+  const size_t need = (size_t)8 * (3 * (size_t)n + S) + 16 * (size_t)std::max(n, 1) + 64;
   if (p->pinned_bytes < need) {
     if (p->pinned) (void)hipHostFree(p->pinned);
     p->pinned = nullptr;
@@ -700,6 +718,7 @@ odf_status odf_compute(odf_plan_t* p, const odf_request* r, odf_stats* stats) {
   double* hA = hV + n;
   unsigned long long* h_nsamp = reinterpret_cast<unsigned long long*>(hA + S);
   int32_t* h_nsurv = reinterpret_cast<int32_t*>(h_nsamp + std::max(n, 1));
+  int32_t* h_nit = h_nsurv + std::max(n, 1);
   std::memcpy(hT, r->T_K, 8 * (size_t)n);
   std::memcpy(hP, r->log10_P_cgs, 8 * (size_t)n);
   std::memcpy(hV, r->vturb_kms, 8 * (size_t)n);
@@ -711,7 +730,6 @@ odf_status odf_compute(odf_plan_t* p, const odf_request* r, odf_stats* stats) {
   HIP_TRY(hipStreamWaitEvent(ps, p->ev_fork, 0));
   HIP_TRY(hipStreamWaitEvent(vs[0], p->ev_fork, 0));
   HIP_TRY(hipStreamWaitEvent(vs[1], p->ev_fork, 0));
-  const size_t osz = (p->opts.precision == ODF_PREC_MIXED ? 4 : 8);
   StageTimer* timer = p->opts.kernel_timing ? &p->timer : nullptr;
   auto enqueue_all = [&]() -> odf_status {
     for (int k = 0; k < NS; ++k)
@@ -731,11 +749,12 @@ odf_status odf_compute(odf_plan_t* p, const odf_request* r, odf_stats* stats) {
       if (es != ODF_OK) return es;
       HIP_TRY(hipMemcpyAsync(h_nsurv + b0, B.nsurv, 4 * nb, hipMemcpyDeviceToHost, ps));
       HIP_TRY(hipMemcpyAsync(h_nsamp + b0, B.nsamp, 8 * nb, hipMemcpyDeviceToHost, ps));
+      HIP_TRY(hipMemcpyAsync(h_nit + b0, B.nit, 4 * nb, hipMemcpyDeviceToHost, ps));
       HIP_TRY(hipEventRecord(p->ev_prep[k], ps));
       // summation on the summing streams in turn
       hipStream_t v = vs[batch & 1];
       HIP_TRY(hipStreamWaitEvent(v, p->ev_prep[k], 0));
-      char* outp = static_cast<char*>(r->out) + (size_t)b0 * p->n_bins * p->n_steps * osz;
+      char* outp = static_cast<char*>(r->out) + (size_t)b0 * out_point_bytes(p);
       es = enqueue_sum(p, B, sb, sl, outp, v, timer);
       if (es != ODF_OK) return es;
       HIP_TRY(hipEventRecord(p->ev_free[k], v));
@@ -757,6 +776,12 @@ odf_status odf_compute(odf_plan_t* p, const odf_request* r, odf_stats* stats) {
   for (hipEvent_t e : p->ev_join) HIP_TRY(hipStreamWaitEvent(s, e, 0));
   HIP_TRY(hipStreamSynchronize(s));
   if (p->opts.kernel_timing) collect_timer(p->timer);
+  for (int i = 0; i < n; ++i)
+    if (h_nit[i] < 0) {
+      set_error("ionisation equilibrium did not converge in %d steps at point %d (T = %g K, log10 P = %g)",
+                -h_nit[i], i, r->T_K[i], r->log10_P_cgs[i]);
+      return ODF_E_INTERNAL;
+    }
   if (stats) {
     std::memset(stats, 0, sizeof *stats);
     stats->state = ODF_DONE;
@@ -840,6 +865,38 @@ odf_status odf_stage_lines(odf_plan_t* p, const odf_request* r, int32_t point, i
     a[i] = h[i].y;
     b[i] = p->lnq / h[i].c1;
   }
+  return ODF_OK;
+}
+
+odf_status odf_stage_state(odf_plan_t* p, const odf_request* r, int32_t point, double* state,
+                           int32_t* iterations) {
+  g_err.clear();
+  if (!p) { set_error("plan is NULL"); return ODF_E_INVALID; }
+  odf_status st = validate_request(p, r, false);
+  if (st != ODF_OK) return st;
+  if (point < 0 || point >= r->n_points) { set_error("point %d out of range", point); return ODF_E_INVALID; }
+  if (!state || !iterations) { set_error("stage_state: NULL output"); return ODF_E_INVALID; }
+  std::lock_guard<std::mutex> guard(p->compute_mu);
+  WorkspaceLease lease(p->loop.get());
+  hipStream_t s = static_cast<hipStream_t>(p->opts.stream);
+  char* base = static_cast<char*>(p->opts.workspace);
+  const SlotLayout& sl = p->compute_slot;
+  HIP_TRY(hipMemcpyAsync(base + sl.off_abund, r->abundance, 8 * p->n_species, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + sl.off_T, r->T_K + point, 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + sl.off_logP, r->log10_P_cgs + point, 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + sl.off_vt, r->vturb_kms + point, 8, hipMemcpyHostToDevice, s));
+  Batch B = make_batch(p, sl, base, 1);
+  HIP_TRY(launch_point_state(s, p->params, B));
+  PointState ps{};
+  int32_t nit = 0;
+  HIP_TRY(hipMemcpyAsync(&ps, B.state, sizeof ps, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&nit, B.nit, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  state[0] = ps.n_e;
+  state[1] = ps.n_heavy;
+  state[2] = ps.n_H;
+  state[3] = ps.rho;
+  *iterations = nit;
   return ODF_OK;
 }
 

@@ -20,6 +20,8 @@ ODF_OK, ODF_E_INVALID, ODF_E_NOMEM, ODF_E_DEVICE, ODF_E_UNKNOWN_TICKET, ODF_E_CA
     0, -1, -2, -3, -4, -5, -6
 PREC = {"fp64": 0, "mixed": 1}
 MEAN = {"geometric": 0, "arithmetic": 1}
+OUTPUT = {"table": 0, "fine": 1}
+ELECTRONS = {"fixed": 0, "equilibrium": 1}
 STATE = {0: "PENDING", 1: "RUNNING", 2: "DONE", 3: "FAILED"}
 
 _D = C.POINTER(C.c_double)
@@ -51,7 +53,7 @@ class OdfOptions(C.Structure):
                 ("kappa_c_power", C.c_double), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_int64), ("stream", C.c_void_p),
                 ("max_batch_points", C.c_int32), ("loop_streams", C.c_int32),
-                ("kernel_timing", C.c_int32)]
+                ("kernel_timing", C.c_int32), ("output", C.c_int32), ("electrons", C.c_int32)]
 
 
 class OdfRequest(C.Structure):
@@ -86,6 +88,7 @@ SIGNATURES = {
     "odf_last_error": (C.c_char_p, []),
     "odf_stage_lines": (C.c_int, [C.c_void_p, C.POINTER(OdfRequest), C.c_int32, _I64, _I64, _I64,
                                   _I32, _I32, _D, _D, _D]),
+    "odf_stage_state": (C.c_int, [C.c_void_p, C.POINTER(OdfRequest), C.c_int32, _D, _I32]),
     "odf_stage_fine": (C.c_int, [C.c_void_p, C.POINTER(OdfRequest), C.c_int32, C.c_void_p]),
     "odf_stage_reduce": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "odf_debug_fail_next_batch": (C.c_int, [C.c_void_p, C.c_int64]),
@@ -217,7 +220,9 @@ class Plan:
                           options.lambda_c_ref_nm, options.kappa_c_power,
                           C.c_void_p(self.workspace.data_ptr()), int(workspace_bytes),
                           C.c_void_p(self.stream.cuda_stream), int(max_batch_points), int(loop_streams),
-                          int(bool(kernel_timing)))
+                          int(bool(kernel_timing)), OUTPUT[getattr(options, "output", "table")],
+                          ELECTRONS[getattr(options, "electrons", "fixed")])
+        self.output = getattr(options, "output", "table")
         h = C.c_void_p()
         _check(lib().odf_plan(C.byref(cl), C.byref(cs), C.byref(self.layout_c), C.byref(opts), C.byref(h)))
         self.handle = h
@@ -248,9 +253,14 @@ class Plan:
     def request_footprint(self, n_points: int) -> int:
         return int(lib().odf_request_footprint(self.handle, int(n_points)))
 
+    def out_shape(self, n_points):
+        """[points][bins][steps] for ODF tables, [points][N] for fine-grid opacity."""
+        if self.output == "fine":
+            return (n_points, self.N)
+        return (n_points, self.n_bins, self.n_steps)
+
     def new_out(self, n_points):
-        return self.torch.empty((n_points, self.n_bins, self.n_steps), dtype=self.out_dtype,
-                                device=self.device)
+        return self.torch.empty(self.out_shape(n_points), dtype=self.out_dtype, device=self.device)
 
     # -- compute ---------------------------------------------------------------
     def compute(self, abundance, points, out=None):
@@ -312,8 +322,8 @@ class Plan:
         t = self.torch
         if out.dtype != self.out_dtype or out.device != self.device or not out.is_contiguous():
             raise ValueError(f"out must be a contiguous {self.out_dtype} tensor on {self.device}")
-        if tuple(out.shape) != (n_points, self.n_bins, self.n_steps):
-            raise ValueError(f"out shape {tuple(out.shape)} != {(n_points, self.n_bins, self.n_steps)}")
+        if tuple(out.shape) != self.out_shape(n_points):
+            raise ValueError(f"out shape {tuple(out.shape)} != {self.out_shape(n_points)}")
         del t
 
     # -- stage entry points ------------------------------------------------------
@@ -331,6 +341,15 @@ class Plan:
         res["n_surv"] = n
         res["voigt_samples"] = nsamp.value
         return res
+
+    def stage_state(self, abundance, points, point=0):
+        """Gas state of one point: dict(n_e, n_heavy, n_H, rho, iterations)."""
+        st = np.zeros(4)
+        it = C.c_int32()
+        r, keep = _request(abundance, points, 0)
+        _check(lib().odf_stage_state(self.handle, C.byref(r), int(point), _ptr(st, _D), C.byref(it)))
+        return dict(n_e=float(st[0]), n_heavy=float(st[1]), n_H=float(st[2]), rho=float(st[3]),
+                    iterations=int(it.value))
 
     def stage_fine(self, abundance, points, point=0):
         kap = self.torch.empty(self.N, dtype=self.out_dtype, device=self.device)

@@ -62,3 +62,24 @@ def log10_err(got, ref):
 
 def fmt(x):
     return f"{x:.3e}" if isinstance(x, float) and math.isfinite(x) else str(x)
+
+
+def compare_points(w, out, prec, bins=None, abundance=None):
+    """Largest relative and log10 errors of out[point][bin][step] against the
+    oracle's ODF, and the number of bins skipped as ambiguous."""
+    a = w.species.abundance if abundance is None else abundance
+    worst, worst_log, skipped = 0.0, 0.0, 0
+    for i in range(w.points.n_points):
+        ref, _, ex = oracle.odf_point(w.lines, w.species, a, float(w.points.T_K[i]),
+                                      float(w.points.log10_P[i]), float(w.points.vturb_kms[i]),
+                                      w.layout, w.options, bins)
+        bsel = np.arange(w.layout.n_bins) if bins is None else np.asarray(bins)
+        amb = ambiguous_bins(ex["lq"], w.layout.bin_edges)
+        got = out[i][bsel]
+        for k, b in enumerate(bsel):
+            if int(b) in amb:
+                skipped += 1
+                continue
+            worst = max(worst, float(rel_err(got[k], ref[k]).max()))
+            worst_log = max(worst_log, float(log10_err(got[k], ref[k]).max()))
+    return worst, worst_log, skipped

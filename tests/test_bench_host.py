@@ -63,3 +63,16 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_pretab_lattice_is_on_the_dfsynthe_grid():
+    import numpy as np
+    import bench
+    from paper_2105_13611_amd import workload as W
+    g = W.dfsynthe_tp_grid()
+    lt = np.log10(2000.0) + (2.0 / 56.0) * np.arange(10, 14)
+    pts = bench._lattice(lt, [0.0, 0.5, 1.0])
+    assert pts.n_points == 12
+    # every lattice node is a point of the 57 x 25 table
+    for T, P in zip(pts.T_K, pts.log10_P):
+        assert np.min(np.abs(g.T_K / T - 1.0) + np.abs(g.log10_P - P)) < 1e-12

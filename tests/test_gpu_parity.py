@@ -13,8 +13,7 @@ import pytest
 
 import oracle
 from paper_2105_13611_amd import workload as W
-from tests.gpu_helpers import (ambiguous_bins, ambiguous_lines, ambiguous_points, floor_values,
-                               log10_err, rel_err)
+from tests.gpu_helpers import ambiguous_lines, ambiguous_points, compare_points, floor_values
 
 pytestmark = pytest.mark.gpu
 
@@ -118,31 +117,12 @@ def test_k4_reduce_given_grid(odf, cfg1, torch, prec, mean):
         np.testing.assert_allclose(out[b], r, rtol=1e-12 if prec == "fp64" else 1e-6)
 
 
-def _compare_points(w, out, prec, bins=None, abundance=None):
-    a = w.species.abundance if abundance is None else abundance
-    worst, worst_log, skipped = 0.0, 0.0, 0
-    for i in range(w.points.n_points):
-        ref, _, ex = oracle.odf_point(w.lines, w.species, a, float(w.points.T_K[i]),
-                                      float(w.points.log10_P[i]), float(w.points.vturb_kms[i]),
-                                      w.layout, w.options, bins)
-        bsel = np.arange(w.layout.n_bins) if bins is None else np.asarray(bins)
-        amb = ambiguous_bins(ex["lq"], w.layout.bin_edges)
-        got = out[i][bsel]
-        for k, b in enumerate(bsel):
-            if int(b) in amb:
-                skipped += 1
-                continue
-            worst = max(worst, float(rel_err(got[k], ref[k]).max()))
-            worst_log = max(worst_log, float(log10_err(got[k], ref[k]).max()))
-    return worst, worst_log, skipped
-
-
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_end_to_end_cfg1(plans1, cfg1, prec):
     w = cfg1
     out, st = plans1[prec].compute(w.species.abundance, w.points)
     out = out.double().cpu().numpy()
-    worst, worst_log, skipped = _compare_points(w, out, prec)
+    worst, worst_log, skipped = compare_points(w, out, prec)
     print(f"cfg1 {prec}: max rel err per step {worst:.3e}, max |dlog10 k| {worst_log:.3e}, "
           f"ambiguous bins skipped {skipped}; stats {st}")
     assert skipped <= 1
@@ -172,7 +152,7 @@ def test_end_to_end_multi_tile_multi_point(odf, multi, prec):
     with odf.plan_for(w, precision=prec, workspace_bytes=24 << 20) as plan:
         out, st = plan.compute(w.species.abundance, w.points)
         out = out.double().cpu().numpy()
-    worst, worst_log, skipped = _compare_points(w, out, prec)
+    worst, worst_log, skipped = compare_points(w, out, prec)
     print(f"multi {prec}: max rel err {worst:.3e}, max |dlog10 k| {worst_log:.3e}, skipped {skipped}")
     assert skipped <= 2
     assert worst <= TOL_STEP[prec]
@@ -192,7 +172,7 @@ def test_end_to_end_three_stages_request_composition(odf, prec):
     with odf.plan_for(w, precision=prec, workspace_bytes=64 << 20) as plan:
         out, st = plan.compute(a, w.points)
         out = out.double().cpu().numpy()
-    worst, worst_log, skipped = _compare_points(w, out, prec, abundance=a)
+    worst, worst_log, skipped = compare_points(w, out, prec, abundance=a)
     print(f"three stages {prec}: max rel err {worst:.3e}, max |dlog10 k| {worst_log:.3e}, "
           f"skipped {skipped}, survivors {st['survivors']}")
     assert skipped <= 2
@@ -238,7 +218,7 @@ def test_edge_layout_tiny_and_huge_bins(odf, prec):
     with odf.plan_for(w, precision=prec, workspace_bytes=64 << 20) as plan:
         out, _ = plan.compute(w.species.abundance, w.points)
         out = out.double().cpu().numpy()
-    worst, _, skipped = _compare_points(w, out, prec)
+    worst, _, skipped = compare_points(w, out, prec)
     assert skipped == 0 and worst <= TOL_STEP[prec]
 
 
@@ -249,7 +229,7 @@ def test_degenerate_no_survivors_and_empty_list(odf, cfg1, prec):
     with odf.plan_for(w, precision=prec, workspace_bytes=64 << 20) as plan:
         out, st = plan.compute(tiny, w.points)
         assert st["survivors"] == 0
-        worst, _, _ = _compare_points(w, out.double().cpu().numpy(), prec, abundance=tiny)
+        worst, _, _ = compare_points(w, out.double().cpu().numpy(), prec, abundance=tiny)
         assert worst <= TOL_STEP[prec]
     empty = replace(w, lines=w.lines.take(np.arange(0)))
     with odf.plan_for(empty, precision=prec, workspace_bytes=64 << 20) as plan:
@@ -267,5 +247,5 @@ def test_options_cutoff_and_cap(odf, multi):
                 points=multi.points.take(np.array([1, 3])))
     with odf.plan_for(w, precision="fp64", workspace_bytes=64 << 20) as plan:
         out, _ = plan.compute(w.species.abundance, w.points)
-    worst, _, skipped = _compare_points(w, out.double().cpu().numpy(), "fp64")
+    worst, _, skipped = compare_points(w, out.double().cpu().numpy(), "fp64")
     assert skipped <= 1 and worst <= TOL_STEP["fp64"]

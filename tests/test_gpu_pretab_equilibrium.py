@@ -1,0 +1,154 @@
+"""GPU parity of the pre-tabulated fine-grid opacity (Sec. 4.1) and of the
+ionisation equilibrium (App. A, without molecules) with the oracle.
+
+Tolerances: fine-grid opacity as the fine-grid stage (1e-10 FP64, 2e-4 FP32,
+relative to the floored value); ODF steps 1e-9 / 1e-3; the equilibrium's n_e
+1e-7 relative (both sides stop once a Newton step changes nothing by 1e-4,
+which leaves an error of the order of that step's square).
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.constants import K_BOLTZ
+from paper_2105_13611_amd import workload as W
+from tests.gpu_helpers import ambiguous_points, compare_points
+
+pytestmark = pytest.mark.gpu
+
+TOL_STEP = {"fp64": 1e-9, "mixed": 1e-3}
+TOL_FINE = {"fp64": 1e-10, "mixed": 2e-4}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def odf(torch):
+    from paper_2105_13611_amd import odf as o
+    o.load_library()
+    return o
+
+
+def _fine_workload():
+    w = W.config(1)
+    pts = W.small_points([5000.0, 3500.0, 12000.0], [4.0, 6.0, 1.0], [2.0, 0.0, 4.0])
+    return replace(w, points=pts, options=replace(w.options, output="fine"))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fine_output_parity(odf, prec):
+    w = _fine_workload()
+    with odf.plan_for(w, precision=prec, workspace_bytes=256 << 20) as plan:
+        out, st = plan.compute(w.species.abundance, w.points)
+        assert tuple(out.shape) == (3, plan.N)
+        out = out.double().cpu().numpy()
+    assert st["state"] == "DONE" and st["points"] == 3
+    for i in range(3):
+        ref, lq = oracle.fine_table_point(w.lines, w.species, w.species.abundance, float(w.points.T_K[i]),
+                                          float(w.points.log10_P[i]), float(w.points.vturb_kms[i]),
+                                          w.layout, w.options)
+        err = np.abs(out[i] - ref) / ref
+        amb = ambiguous_points(lq, ref.size)
+        err[amb] = 0.0
+        print(f"fine {prec} point {i}: max err {err.max():.3e}, ambiguous {amb.size}")
+        assert err.max() <= TOL_FINE[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fine_output_equals_one_point_bin_table(odf, prec):
+    # the same kernels up to the reduction: the fine output must equal, bit
+    # for bit, the arithmetic-mean ODF of bins of one point with one sub-bin
+    w = _fine_workload()
+    N = W.grid_size(w.layout.lambda_first_nm, w.layout.lambda_last_nm, w.layout.resolving_power)
+    one = W.Layout(w.layout.lambda_first_nm, w.layout.lambda_last_nm, w.layout.resolving_power,
+                   np.arange(N + 1, dtype=np.int64), np.array([1.0]))
+    wt = replace(w, layout=one, options=replace(w.options, output="table", mean="arithmetic"))
+    with odf.plan_for(w, precision=prec, workspace_bytes=256 << 20) as pf, \
+            odf.plan_for(wt, precision=prec, workspace_bytes=256 << 20) as pt:
+        a, _ = pf.compute(w.species.abundance, w.points)
+        b, _ = pt.compute(w.species.abundance, w.points)
+    assert tuple(b.shape) == (3, N, 1)
+    assert bool((a == b[:, :, 0]).all())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fine_output_request_loop_and_batches(odf, prec):
+    # request loop, batches of one point, and one batch give the same bits
+    w = _fine_workload()
+    with odf.plan_for(w, precision=prec, workspace_bytes=256 << 20) as p1:
+        a, _ = p1.compute(w.species.abundance, w.points)
+        t, b = p1.submit(w.species.abundance, w.points)
+        assert p1.wait(t)["state"] == "DONE"
+    with odf.plan_for(w, precision=prec, workspace_bytes=256 << 20, max_batch_points=1) as p2:
+        c, _ = p2.compute(w.species.abundance, w.points)
+    assert bool((a == b).all()) and bool((a == c).all())
+
+
+def _grid_sample():
+    g = W.dfsynthe_tp_grid()
+    idx = np.unique(np.concatenate([[0, 24, 1400, 1424], np.arange(3, 1425, 37)]))
+    return W.Points(g.T_K[idx], g.log10_P[idx], g.vturb_kms[idx])
+
+
+@pytest.mark.parametrize("cfg", [2, 5])
+def test_equilibrium_state_parity(odf, cfg):
+    # cfg 5 has 80 species (more than one per lane) and three stages
+    w = W.config(cfg, n_lines=2000, lam_range=(300.0, 302.0), n_bins=2, n_requests=1)
+    w = replace(w, options=replace(w.options, electrons="equilibrium"))
+    pts = _grid_sample()
+    sp = w.species
+    worst, steps = 0.0, []
+    with odf.plan_for(w, precision="fp64", workspace_bytes=64 << 20) as plan:
+        for i in range(pts.n_points):
+            T, lp = float(pts.T_K[i]), float(pts.log10_P[i])
+            got = plan.stage_state(sp.abundance, pts, i)
+            ref = oracle.ionisation_equilibrium(T, lp, sp.abundance, sp.chi_ev, sp.part_fn)
+            assert ref["converged"] and got["iterations"] > 0
+            assert abs(got["iterations"] - ref["iterations"]) <= 1
+            e = abs(got["n_e"] / ref["n_e"] - 1.0)
+            worst = max(worst, e)
+            steps.append(got["iterations"])
+            st = oracle.point_state(T, lp, 0.1, sp.abundance, sp.mass_amu, n_e=ref["n_e"])
+            assert got["n_heavy"] == pytest.approx(st["n_heavy"], rel=1e-7)
+            assert got["n_H"] == pytest.approx(st["n_H"], rel=1e-7)
+            assert got["rho"] == pytest.approx(st["rho"], rel=1e-7)
+            assert got["n_heavy"] + got["n_e"] == pytest.approx(10.0 ** lp / (K_BOLTZ * T), rel=1e-12)
+    print(f"cfg{cfg} equilibrium: {pts.n_points} points, max rel err n_e {worst:.3e}, "
+          f"Newton steps {min(steps)}..{max(steps)}")
+    assert worst <= 1e-7
+
+
+def test_fixed_electron_pressure_state(odf):
+    w = W.config(1)
+    pts = W.small_points([5000.0], [4.0], [2.0])
+    with odf.plan_for(w, precision="fp64", workspace_bytes=64 << 20) as plan:
+        got = plan.stage_state(w.species.abundance, pts, 0)
+    assert got["iterations"] == 0
+    assert got["n_e"] == pytest.approx(0.1 * 1e4 / (K_BOLTZ * 5000.0), rel=1e-14)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_equilibrium_end_to_end(odf, prec):
+    w = W.config(5, n_lines=40_000, lam_range=(300.0, 345.0), n_bins=7, n_requests=1)
+    w = replace(w, options=replace(w.options, electrons="equilibrium"),
+                points=W.Points(np.array([2500.0, 6000.0, 15000.0, 200000.0]),
+                                np.array([6.0, -2.0, 3.0, -4.0]),
+                                np.array([1.0, 2.0, 0.0, 4.0])))
+    with odf.plan_for(w, precision=prec, workspace_bytes=64 << 20) as plan:
+        out, st = plan.compute(w.species.abundance, w.points)
+        t, out2 = plan.submit(w.species.abundance, w.points)
+        assert plan.wait(t)["state"] == "DONE"
+        assert bool((out == out2).all())
+        out = out.double().cpu().numpy()
+    worst, worst_log, skipped = compare_points(w, out, prec)
+    print(f"equilibrium {prec}: max rel err {worst:.3e}, max |dlog10 k| {worst_log:.3e}, "
+          f"skipped {skipped}, survivors {st['survivors']}")
+    assert skipped <= 2
+    assert worst <= TOL_STEP[prec]
