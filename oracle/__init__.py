@@ -17,4 +17,4 @@ from .physics import (point_state, stage_fractions, populations, line_quantities
                       ionisation_equilibrium, electron_density, saha_ratios)
 from .voigt import voigt_h  # noqa: F401
 from .odf import (grid_size, grid_lambda_nm, fine_opacity, odf_reduce_bin, odf_point, odf,  # noqa: F401
-                  fine_table_point)
+                  fine_table_point, slab_fine_intensity, slab_odf_intensity)

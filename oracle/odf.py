@@ -17,6 +17,13 @@
 * Pre-tabulated high-resolution opacity (Sec. 4.1, option to pre-tabulate):
   the table in ODF form with one sub-bin per fine point, i.e. the floored
   opacity of every point of the grid.
+* A consumer of the ODF with no dataset: the emergent intensity of an
+  isothermal slab of column mass m, in units of the Planck function,
+  I(kappa) = 1 - exp(-(kappa + kappa_c) m).  The bin intensity from the fine
+  grid is the equal-weight mean over the bin's points (the sum I_N of
+  Sec. 2.3 with the bin's steps taken as equal); from the ODF it is the sum
+  over sub-bins weighted by their widths (Sec. 2.3, I_ODF; App. E, the
+  weighted sum over sub-bins with the continuum added to every sub-bin).
 """
 import math
 
@@ -26,7 +33,7 @@ from .physics import grid_size, kappa_c, line_quantities
 from .voigt import voigt_h
 
 __all__ = ["grid_size", "grid_lambda_nm", "fine_opacity", "odf_reduce_bin",
-           "odf_point", "odf", "fine_table_point"]
+           "odf_point", "odf", "fine_table_point", "slab_fine_intensity", "slab_odf_intensity"]
 
 _CHUNK_SAMPLES = 4_000_000
 
@@ -129,6 +136,24 @@ def fine_table_point(lines, species, abundance, T, log10_P, vturb, layout, opts,
     kl = fine_opacity(lq, layout, j0, j1)
     floor = opts.cutoff * kappa_c(grid_lambda_nm(layout, np.arange(j0, j1)), opts)
     return np.maximum(kl, floor), lq
+
+
+def slab_fine_intensity(kappa_bin, kappa_c, column):
+    """Fine-grid bin intensity of the slab: mean over the bin of
+    1 - exp(-(kappa_j + kappa_c) m), for every column m given."""
+    k = np.asarray(kappa_bin, dtype=np.float64)[None, :]
+    m = np.atleast_1d(np.asarray(column, dtype=np.float64))[:, None]
+    return np.mean(-np.expm1(-(k + kappa_c) * m), axis=1)
+
+
+def slab_odf_intensity(steps, step_frac, kappa_c, column):
+    """ODF bin intensity of the slab: sum over sub-bins of their width
+    fraction times 1 - exp(-(kappa_s + kappa_c) m)."""
+    f = np.asarray(step_frac, dtype=np.float64)
+    f = f / f.sum()
+    k = np.asarray(steps, dtype=np.float64)[None, :]
+    m = np.atleast_1d(np.asarray(column, dtype=np.float64))[:, None]
+    return np.sum(f[None, :] * -np.expm1(-(k + kappa_c) * m), axis=1)
 
 
 def _odf_task(args):

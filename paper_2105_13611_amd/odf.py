@@ -233,6 +233,8 @@ class Plan:
         if getattr(self, "handle", None) is not None and self.handle.value:
             lib().odf_plan_destroy(self.handle)
             self.handle = None
+        # the library no longer uses the workspace: release it
+        self.workspace = None
 
     def __del__(self):
         try:

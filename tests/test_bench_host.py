@@ -6,6 +6,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 import bench
 from paper_2105_13611_amd import workload as W
@@ -76,3 +77,40 @@ def test_pretab_lattice_is_on_the_dfsynthe_grid():
     # every lattice node is a point of the 57 x 25 table
     for T, P in zip(pts.T_K, pts.log10_P):
         assert np.min(np.abs(g.T_K / T - 1.0) + np.abs(g.log10_P - P)) < 1e-12
+
+
+def test_subbin_combination_matches_a_direct_reduction():
+    # sub-bins built from 200 elementary sub-bins equal the ODF reduced
+    # with those borders directly (the geometric mean of a union of
+    # equal-width sub-bins is the geometric mean of their means)
+    import numpy as np
+    import bench
+    import oracle
+    rng = np.random.default_rng(4)
+    for n in (1000, 1733):
+        v = 10.0 ** rng.uniform(-2, 6, n)
+        for mean in ("geometric", "arithmetic"):
+            elem = oracle.odf_reduce_bin(v, np.full(bench.N_ELEMENTARY, 1.0 / bench.N_ELEMENTARY), mean)
+            for bs in [(0.9,), (0.8, 0.95), (0.5, 0.85, 0.99)]:
+                fr = np.diff(np.concatenate([[0.0], bs, [1.0]]))
+                got = bench.combine_steps(elem, bs, mean)
+                np.testing.assert_allclose(got, oracle.odf_reduce_bin(v, fr, mean), rtol=1e-12)
+
+
+def test_slab_error_matches_the_oracle_slab():
+    import numpy as np
+    import bench
+    import oracle
+    rng = np.random.default_rng(8)
+    P, B, n = 2, 3, 300
+    fr = np.array([0.7, 0.25, 0.05])
+    kc = rng.uniform(0.2, 0.8, B)
+    vals = 10.0 ** rng.uniform(-3, 5, (P, B, n))
+    steps = np.array([[oracle.odf_reduce_bin(vals[p, b], fr, "geometric") for b in range(B)] for p in range(P)])
+    cols = bench.slab_columns(kc)
+    fine_I = np.array([[oracle.slab_fine_intensity(vals[p, b], kc[b], cols[b]) for b in range(B)]
+                       for p in range(P)])
+    ref = max(abs(oracle.slab_odf_intensity(steps[p, b], fr, kc[b], cols[b])[c] / fine_I[p, b, c] - 1.0)
+              for p in range(P) for b in range(B) for c in range(cols.shape[1]))
+    assert bench.slab_odf_error(steps, fr, fine_I, kc, cols) == pytest.approx(ref, rel=1e-12)
+    np.testing.assert_allclose(cols * kc[:, None], np.tile(bench.SLAB_TAU_C, (B, 1)), rtol=1e-15)

@@ -121,3 +121,44 @@ def test_fine_table_is_the_odf_of_one_point_bins(cfg1, mean):
     part, _ = oracle.fine_table_point(w.lines, w.species, w.species.abundance, 5000.0, 4.0, 2.0,
                                       w.layout, opts, 4000, 4100)
     np.testing.assert_allclose(part, fine[4000:4100], rtol=1e-13)
+
+
+COLUMNS = np.array([1e-3, 1e-2, 0.1, 1.0, 10.0, 100.0])
+
+
+def test_slab_constant_bin_is_exact():
+    # a flat bin: every sub-bin mean is the value, so any ODF is exact
+    v = np.full(500, 37.5)
+    for fr in (STEPS12, np.array([0.9, 0.1]), np.array([0.5, 0.3, 0.15, 0.05])):
+        for mean in ("geometric", "arithmetic"):
+            st = odf_reduce_bin(v, fr, mean)
+            np.testing.assert_allclose(oracle.slab_odf_intensity(st, fr, 0.4, COLUMNS),
+                                       oracle.slab_fine_intensity(v, 0.4, COLUMNS), rtol=1e-14)
+
+
+def test_slab_one_point_sub_bins_reproduce_the_fine_grid():
+    rng = np.random.default_rng(11)
+    v = 10.0 ** rng.uniform(-3, 5, 40)
+    fr = np.full(40, 1.0 / 40)
+    for mean in ("geometric", "arithmetic"):
+        st = odf_reduce_bin(v, fr, mean)
+        np.testing.assert_allclose(oracle.slab_odf_intensity(st, fr, 0.3, COLUMNS),
+                                   oracle.slab_fine_intensity(v, 0.3, COLUMNS), rtol=1e-12)
+
+
+def test_slab_thin_and_thick_limits():
+    rng = np.random.default_rng(12)
+    v = 10.0 ** rng.uniform(-2, 4, 1000)
+    fr = np.array([0.7, 0.2, 0.08, 0.02])
+    thin = np.array([1e-12])
+    ar = odf_reduce_bin(v, fr, "arithmetic")
+    ge = odf_reduce_bin(v, fr, "geometric")
+    ref = oracle.slab_fine_intensity(v, 0.5, thin)
+    # optically thin: I is linear in kappa, so the arithmetic mean is exact
+    # and the geometric mean (below the arithmetic one) under-estimates
+    assert oracle.slab_odf_intensity(ar, fr, 0.5, thin)[0] == pytest.approx(ref[0], rel=1e-9)
+    assert oracle.slab_odf_intensity(ge, fr, 0.5, thin)[0] < ref[0] * (1 - 1e-3)
+    # optically thick: every form saturates at the Planck function
+    thick = np.array([1e6])
+    assert oracle.slab_odf_intensity(ge, fr, 0.5, thick)[0] == pytest.approx(1.0, abs=1e-12)
+    assert oracle.slab_fine_intensity(v, 0.5, thick)[0] == pytest.approx(1.0, abs=1e-12)
