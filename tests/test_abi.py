@@ -65,7 +65,7 @@ def _plan_args(w, **over):
 
 
 @pytest.mark.parametrize("case", ["species", "stage", "lambda", "edges", "frac", "cutoff", "workspace",
-                                  "nan_gf"])
+                                  "nan_gf", "output", "electrons", "pe_over_p"])
 def test_plan_rejects_bad_arguments_before_touching_the_device(lib, case):
     w = workload.config(1, n_lines=50)
     over = {}
@@ -88,6 +88,12 @@ def test_plan_rejects_bad_arguments_before_touching_the_device(lib, case):
         opts.cutoff = float("nan")
     if case == "workspace":
         opts.workspace = None
+    if case == "output":
+        opts.output = 2
+    if case == "electrons":
+        opts.electrons = -1
+    if case == "pe_over_p":
+        opts.pe_over_p = 1.5          # checked while the electron pressure is fixed
     h = C.c_void_p()
     rc = lib.odf_plan(C.byref(cl), C.byref(cs), C.byref(lay), C.byref(opts), C.byref(h))
     assert rc == odf.ODF_E_INVALID
@@ -103,3 +109,4 @@ def test_null_arguments(lib):
     assert lib.odf_submit(None, None, None) == odf.ODF_E_INVALID
     assert lib.odf_poll(None, 1, None) == odf.ODF_E_INVALID
     assert lib.odf_point_footprint(None) == -1
+    assert lib.odf_stage_state(None, None, 0, None, None) == odf.ODF_E_INVALID
