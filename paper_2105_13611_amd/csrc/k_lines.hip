@@ -559,8 +559,9 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
       czh = e.a < kFarR64 ? zone_half(kFarR64, c1) : -1;
       z40 = e.a < kFar4R64 ? zone_half(kFar4R64, c1) : -1;
     } else {
-      const int32_t far = e.a < kFarR32 ? zone_half(kFarR32, c1) : -1;
-      const int32_t ring = e.a < kRingR32 ? zone_half(kRingR32, c1) : -1;
+      // no zone: -32768, which the Voigt kernel's row masks read as empty
+      const int32_t far = e.a < kFarR32 ? min(zone_half(kFarR32, c1), 32767) : -32768;
+      const int32_t ring = e.a < kRingR32 ? min(zone_half(kRingR32, c1), 32767) : -32768;
       czh = (int32_t)(((uint32_t)ring << 16) | ((uint32_t)far & 0xffffu));
     }
     if (kRec64) {

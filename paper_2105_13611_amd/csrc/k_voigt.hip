@@ -184,6 +184,21 @@ __device__ __forceinline__ unsigned zone_rows(int J, int half, int t_lo) {
   return ((2u << hi) - 1u) & ~((1u << lo) - 1u);
 }
 
+// Bit mask of the rows (of the wave's 16) that meet [a, b], both relative to
+// the tile's first point, uniform and of any sign; empty when b < a by 64 or
+// more or when the interval misses the tile.  Branch-free scalar arithmetic
+// (the empty asm keeps each clamp a pair of scalar min/max instead of a
+// vector three-operand clamp read back into scalar registers).
+__device__ __forceinline__ unsigned rows_between(int a, int b) {
+  int lo = max(a >> 6, 0);
+  asm("" : "+s"(lo));
+  lo = min(lo, kRows);
+  int hi = max(b >> 6, -1);
+  asm("" : "+s"(hi));
+  hi = min(hi, kRows - 1);
+  return (0xffffu << lo) & (0xffffu >> (kRows - 1 - hi));
+}
+
 __device__ __forceinline__ float far_value(float u, const Far32& f) {
   const float u2 = u * u;
   return fmaf(u2, f.A, f.B) * __builtin_amdgcn_rcpf(fmaf(u2, u2 + f.K1, f.K2));
@@ -238,20 +253,21 @@ __device__ __forceinline__ void line32(const Rec32& l, int t_lo, int t_hi, int l
   f.B = l.B;
   f.K1 = l.K1;
   f.K2 = l.K2;
-  const int ib = l.J - t_lo - lane;
+  const int rel = l.J - t_lo;
+  const int ib = rel - lane;
   const float d0 = (float)ib + l.phi;
-  const int zfar = (int)(short)(l.czh & 0xffff);   // |x| < 15 zone half-width
-  const int zring = l.czh >> 16;                   // |x| < 6 zone half-width
-  const unsigned near = zone_rows(l.J, zfar, t_lo);
+  // zone half-widths (a sentinel of -32768 makes a zone empty)
+  const int zfar = (int)(short)(l.czh & 0xffff);   // |x| < 15
+  const int zring = l.czh >> 16;                   // |x| < 6
+  const unsigned near = rows_between(rel - zfar, rel + zfar);
   const int jl = max(l.jlo, t_lo) - t_lo;
   const int jh = min(l.jhi, t_hi) - t_lo;
-  const int r_lo = jl >> 6, r_hi = jh >> 6;
-  const unsigned rows = ((2u << r_hi) - 1u) & ~((1u << r_lo) - 1u);
-  // rows cut by the window edge (at most two); lanes past the grid's end are
-  // summed like the others and never stored
-  unsigned edge = 0u;
-  if (l.jlo > t_lo + 64 * r_lo) edge |= 1u << r_lo;
-  if (l.jhi < t_lo + 64 * r_hi + 63) edge |= 1u << r_hi;
+  const int r_lo = jl >> 6, r_hi = jh >> 6;   // 0 <= jl <= jh <= 1023 here
+  const unsigned rows = (0xffffu << r_lo) & (0xffffu >> (kRows - 1 - r_hi));
+  // rows cut by the window edge (at most two): the window starts inside its
+  // first row or ends inside its last; lanes past the grid's end are summed
+  // like the others and never stored
+  const unsigned edge = ((jl & 63) ? (1u << r_lo) : 0u) | ((jh & 63) != 63 ? (1u << r_hi) : 0u);
   const unsigned nearr = near & rows;
   // kept in a scalar register, so that the masks stay scalar operations
   unsigned ne = near | edge;
@@ -261,7 +277,7 @@ __device__ __forceinline__ void line32(const Rec32& l, int t_lo, int t_hi, int l
   if (!m) return;
   // edge rows and rows near the core: per-lane masks, partial sums in LDS
   // (near rows exist only for a < 15, where sigma = 1 and u = x)
-  const unsigned core = zone_rows(l.J, zring, t_lo);
+  const unsigned core = rows_between(rel - zring, rel + zring);
   const float y = l.y, S = l.S;
   const float y2 = y * y;
   const bool ser = y < kSerYMax;
@@ -298,6 +314,32 @@ __device__ __forceinline__ void flush32(float (&s)[kRows], float (&p)[kRows],
     lp[o] = 0.0f;
     p[rr] = 0.0f;
   }
+}
+
+// A whole record with one scalar-memory wait.  Left to itself the compiler
+// loads each field where it is first used, behind the branches of the line
+// routine, and waits for scalar memory three times per line; the empty asm
+// that takes all twelve words in scalar registers puts the loads and their
+// single wait here.
+__device__ __forceinline__ Rec32 load_rec32(const Rec32* __restrict__ p) {
+  const int4* q = reinterpret_cast<const int4*>(p);
+  const int4 a = q[0], b = q[1], c = q[2];
+  asm volatile("" ::"s"(a.x), "s"(a.y), "s"(a.z), "s"(a.w), "s"(b.x), "s"(b.y), "s"(b.z), "s"(b.w),
+               "s"(c.x), "s"(c.y), "s"(c.z), "s"(c.w));
+  Rec32 r;
+  r.J = a.x;
+  r.jlo = a.y;
+  r.jhi = a.z;
+  r.czh = a.w;
+  r.phi = __int_as_float(b.x);
+  r.c1 = __int_as_float(b.y);
+  r.A = __int_as_float(b.z);
+  r.B = __int_as_float(b.w);
+  r.K1 = __int_as_float(c.x);
+  r.K2 = __int_as_float(c.y);
+  r.S = __int_as_float(c.z);
+  r.y = __int_as_float(c.w);
+  return r;
 }
 
 // lines summed in plain FP32 between two compensated additions (the plain
@@ -361,9 +403,9 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
     if (base + 64 + lane < c1) nxt = win[base + 64 + lane];
     unsigned long long m = __ballot(cur.x <= t_hi && cur.y >= t_lo);
     while (m) {
-      const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);
+      const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(m));
       m &= m - 1;
-      line32(rec[base + k], t_lo, t_hi, lane, lnq2, lnq6, q64, g64, Q, lds_ser, p, lp);
+      line32(load_rec32(rec + base + k), t_lo, t_hi, lane, lnq2, lnq6, q64, g64, Q, lds_ser, p, lp);
       if (++since_flush == kFlushLines) {
         flush32(s, p, lp, lc, lane);
         since_flush = 0;

@@ -120,7 +120,7 @@ struct PointState {
 struct alignas(16) Rec32 {
   int32_t J;        // nearest integer of the fractional centre index
   int32_t jlo, jhi; // window, clipped to the grid
-  int32_t czh;      // zone half-widths: low 16 bits |x| < 15, high 16 bits |x| < 6 (-1: none)
+  int32_t czh;      // zone half-widths: low 16 bits |x| < 15, high 16 bits |x| < 6 (-32768: none)
   float phi;        // fractional centre minus J, in [-1/2, 1/2]
   float c1;         // sigma ln q / b, so u ~= d c1 (1 + d ln q / 2 + ...)
   float A, B, K1, K2;   // far-wing fraction (above)
