@@ -583,6 +583,28 @@ __device__ __forceinline__ void line64(const Rec64& l, int t_lo, int t_hi, int l
   }
 }
 
+// A whole FP64 record with one scalar-memory wait (as load_rec32).
+__device__ __forceinline__ Rec64 load_rec64(const Rec64* __restrict__ p) {
+  const int4* q = reinterpret_cast<const int4*>(p);
+  const int4 a = q[0], b = q[1], c = q[2], d = q[3];
+  asm volatile("" ::"s"(a.x), "s"(a.y), "s"(a.z), "s"(a.w), "s"(b.x), "s"(b.y), "s"(c.x), "s"(c.y),
+               "s"(c.z), "s"(c.w), "s"(d.x), "s"(d.y), "s"(d.z), "s"(d.w));
+  Rec64 r;
+  r.J = a.x;
+  r.jlo = a.y;
+  r.jhi = a.z;
+  r.czh = a.w;
+  r.z40 = b.x;
+  r.li = b.y;
+  r.pad0 = b.z;
+  r.pad1 = b.w;
+  r.phi = __hiloint2double(c.y, c.x);
+  r.S = __hiloint2double(c.w, c.z);
+  r.y = __hiloint2double(d.y, d.x);
+  r.c1 = __hiloint2double(d.w, d.z);
+  return r;
+}
+
 // Four workgroups per CU (4 waves per SIMD, at most 128 VGPRs): a few
 // registers spill, and that measured 6 % faster than 3 waves without spills.
 __global__ __launch_bounds__(256, 4) void k_voigt64(Params P, Batch B, const QuadConsts* __restrict__ Q,
@@ -627,7 +649,7 @@ __global__ __launch_bounds__(256, 4) void k_voigt64(Params P, Batch B, const Qua
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);
       m &= m - 1;
-      line64(rec[base + k], t_lo, t_hi, lane, lnq, q64, g64, Q, as, ls);
+      line64(load_rec64(rec + base + k), t_lo, t_hi, lane, lnq, q64, g64, Q, as, ls);
     }
   }
   double* kap = reinterpret_cast<double*>(B.kappa) + p * B.kappa_stride;
