@@ -52,10 +52,10 @@ WORKLOADS = {
 # u from the index at the first of eight rows 6/8, u^2 1, numerator 2,
 # denominator 3, reciprocal 1, accumulate 2, compensated add every 64 lines 4/64
 FLOP_PER_SAMPLE_F32 = 11.8
-# FP64 far wing (four-node pair): x carried 2, x^2 1, r^2 1, two pairs
-# 2*(1+1+2), numerator 5, product 1, reciprocal with two Newton steps 9,
-# scale 4, accumulate 1
-FLOP_PER_SAMPLE_F64 = 32
+# FP64 far wing (four-node pair as one fraction in X = x^2): x carried 2,
+# X 1, numerator and denominator Horner chains 14, reciprocal with one Newton
+# step 5, product and accumulate 3, edge mask 3
+FLOP_PER_SAMPLE_F64 = 28
 # VALU peak without packed FP32 (disabled in this build): 256 CU x 4 SIMD x
 # 16 lanes x 2 FLOP per FMA x 2.4 GHz
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
