@@ -140,10 +140,12 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def traffic_per_launch(precision):
+def traffic_per_launch(precision, samples_per_launch=None):
     """HBM bytes per Voigt launch from the committed counter summary of the
     full-table run (FETCH_SIZE + WRITE_SIZE, each scaled by its copy-kernel
-    calibration), or None when there is none or the kernel has changed."""
+    calibration), or None when there is none or the kernel has changed.
+    Given this run's samples per launch, the summary's bytes per sample are
+    scaled to it (the same table may be cut into launches differently)."""
     path = os.path.join(ROOT, "profiles", f"voigt{32 if precision == 'mixed' else 64}_full_table_hbm_traffic.md")
     if not os.path.exists(path):
         return None
@@ -154,6 +156,8 @@ def traffic_per_launch(precision):
     d = json.loads(txt[i + 7: txt.index("```", i + 7)])
     if d.get("source_sha256") != kernel_sources_sha256():
         return None
+    if samples_per_launch is not None and "hbm_bytes_per_sample" in d:
+        return d["hbm_bytes_per_sample"] * samples_per_launch
     return d["hbm_bytes_per_launch"]
 
 
@@ -169,7 +173,7 @@ def roofline(res, flop_per_sample, precision):
     flop_per_launch = samples * flop_per_sample / launches
     achieved = flop_per_launch / (busy / 1e3 / launches) / 1e12
     out = dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
-               frac=achieved / PEAK_VALU_TFLOPS, traffic=traffic_per_launch(precision),
+               frac=achieved / PEAK_VALU_TFLOPS, traffic=traffic_per_launch(precision, samples / launches),
                kernel="voigt scatter-sum", avg_launch_ms=ms / launches,
                busy_ms_per_launch=busy / launches, launches=launches,
                samples_per_launch=samples / launches, flop_per_sample=flop_per_sample)

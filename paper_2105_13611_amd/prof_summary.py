@@ -85,6 +85,12 @@ def traffic(args):
                    copy_bytes=copy_bytes, fetch_factor=res["FETCH_SIZE"]["factor"],
                    write_factor=res["WRITE_SIZE"]["factor"],
                    copy_fetch_kib=res["FETCH_SIZE"]["copy_kib"], copy_write_kib=res["WRITE_SIZE"]["copy_kib"])
+    if args.bench_log:
+        # per Voigt sample, so that a run batched differently can scale it
+        j = json.loads([l for l in open(args.bench_log) if l.startswith("{")][-1])
+        samples = j["voigt_samples_per_point"] * j["config"]["points"] * j["steps"]
+        summary["voigt_samples"] = samples
+        summary["hbm_bytes_per_sample"] = hbm * summary["launches"] / samples
     lines = [f"# HBM traffic of {args.kernel}", "", args.title, "",
              "Commands (run from the repository root on one MI355X, one counter per pass):", "",
              "```", args.command, "```", "",
@@ -93,7 +99,8 @@ def traffic(args):
              f"(WRITE_SIZE); factors {summary['fetch_factor']:.4f} and {summary['write_factor']:.4f}",
              f"- {args.kernel}: {summary['launches']} launches, "
              f"{summary['fetch_bytes_per_launch'] / 1e9:.3f} GB read and "
-             f"{summary['write_bytes_per_launch'] / 1e9:.3f} GB written per launch (calibrated)",
+             f"{summary['write_bytes_per_launch'] / 1e9:.3f} GB written per launch (calibrated)"
+             + (f"; {summary['hbm_bytes_per_sample']:.4f} B per Voigt sample" if "hbm_bytes_per_sample" in summary else ""),
              "", "```json", json.dumps(summary, indent=1), "```", ""]
     open(args.out, "w").write("\n".join(lines))
 
@@ -142,6 +149,7 @@ def main():
     b.add_argument("--write", required=True)
     b.add_argument("--copy-mb", type=int, required=True)
     b.add_argument("--kernel", required=True)
+    b.add_argument("--bench-log", default="", help="benchmark line of the FETCH_SIZE run (samples)")
     b.add_argument("--command", required=True)
     b.add_argument("--title", default="")
     b.add_argument("--out", required=True)
