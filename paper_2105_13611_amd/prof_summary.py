@@ -5,6 +5,9 @@
   python -m paper_2105_13611_amd.prof_summary traffic --fetch <counter csv>
       --write <counter csv> --copy-mb 1024 --kernel k_voigt32
       --command "<profiled command>" --out profiles/<name>.md
+  python -m paper_2105_13611_amd.prof_summary passes --fetch <counter csv>
+      --write <counter csv> --trace <run_kernel_trace.csv> --copy-mb 1024
+      --command "<profiled commands>" --out profiles/<name>.md
   python -m paper_2105_13611_amd.prof_summary flops --csv <counter csv>
       --bench-log <the profiled run's output> --kernel k_voigt32
       --command "<profiled command>" --out profiles/<name>.md
@@ -105,6 +108,46 @@ def traffic(args):
     open(args.out, "w").write("\n".join(lines))
 
 
+def passes(args):
+    """HBM bytes (calibrated FETCH_SIZE + WRITE_SIZE) and the rate over the
+    traced durations of every engine kernel of one profiled table run."""
+    copy_bytes = args.copy_mb << 20
+    per = {}
+    factors = {}
+    for counter, path in (("FETCH_SIZE", args.fetch), ("WRITE_SIZE", args.write)):
+        d = per_dispatch(path, counter)
+        copies = sorted(v for n, v in d.values() if "elementwise" in n or "mul" in short_name(n))[-3:]
+        factors[counter] = copy_bytes / (sum(copies) / len(copies) * 1024.0)
+        for n, v in d.values():
+            if "odf::" not in n or not short_name(n).startswith("k_"):
+                continue
+            e = per.setdefault(short_name(n), {"FETCH_SIZE": [], "WRITE_SIZE": []})
+            e[counter].append(factors[counter] * 1024.0 * v)
+    dur = defaultdict(list)
+    for r in csv.DictReader(open(args.trace)):
+        n = r["Kernel_Name"]
+        if "odf::" in n and short_name(n).startswith("k_"):
+            dur[short_name(n)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    lines = [f"# HBM traffic of every pass: {args.title}", "",
+             "Commands (run from the repository root on one MI355X, one counter per pass):", "",
+             "```", args.command, "```", "",
+             f"- calibration factors (elementwise copy of {args.copy_mb} MiB): FETCH_SIZE "
+             f"{factors['FETCH_SIZE']:.4f}, WRITE_SIZE {factors['WRITE_SIZE']:.4f}",
+             "- durations are the kernel trace's per-dispatch times of the same table in another run; "
+             "kernels of the three internal streams overlap, so a dispatch's time includes time it "
+             "shares the GPU and the rates are lower bounds", "",
+             "| kernel | launches | GB read per launch | GB written per launch | avg ms (trace) | GB/s | fraction of 8 TB/s |",
+             "|---|---|---|---|---|---|---|"]
+    for k in sorted(per, key=lambda k: -sum(per[k]["FETCH_SIZE"])):
+        f, w = per[k]["FETCH_SIZE"], per[k]["WRITE_SIZE"]
+        n = max(len(f), 1)
+        rd, wr = sum(f) / n, (sum(w) / len(w) if w else 0.0)
+        t = sum(dur[k]) / len(dur[k]) if dur.get(k) else 0.0
+        rate = (rd + wr) / t / 1e9 if t > 0 else 0.0
+        lines.append(f"| {k} | {n} | {rd / 1e9:.3f} | {wr / 1e9:.3f} | {t * 1e3:.3f} | {rate:.1f} | {rate / 8000.0:.4f} |")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
 def flops(args):
     """Executed floating-point operations of one kernel from the VALU counters
     (wave instructions x 64 lanes; FMA = 2), per Voigt sample of the profiled
@@ -153,6 +196,14 @@ def main():
     b.add_argument("--command", required=True)
     b.add_argument("--title", default="")
     b.add_argument("--out", required=True)
+    e = sub.add_parser("passes")
+    e.add_argument("--fetch", required=True)
+    e.add_argument("--write", required=True)
+    e.add_argument("--trace", required=True)
+    e.add_argument("--copy-mb", type=int, required=True)
+    e.add_argument("--command", required=True)
+    e.add_argument("--title", default="")
+    e.add_argument("--out", required=True)
     c = sub.add_parser("flops")
     c.add_argument("--csv", required=True)
     c.add_argument("--bench-log", required=True)
@@ -161,7 +212,7 @@ def main():
     c.add_argument("--title", default="")
     c.add_argument("--out", required=True)
     args = ap.parse_args()
-    {"stats": stats, "traffic": traffic, "flops": flops}[args.cmd](args)
+    {"stats": stats, "traffic": traffic, "passes": passes, "flops": flops}[args.cmd](args)
 
 
 if __name__ == "__main__":
