@@ -287,6 +287,12 @@ odf_status odf_stage_times(odf_plan_t *plan, double *ms, double *busy_ms, int64_
  * ticket ends FAILED while every other ticket completes normally. */
 odf_status odf_debug_fail_next_batch(odf_plan_t *plan, int64_t ticket);
 
+/* Test hook for failure handling: the ionisation equilibrium of this plan
+ * may take at most max_steps Newton steps (1..1000; 100 by default), so a
+ * test can make points fail to converge from the host.  Waits for the
+ * request loop to be idle.  ODF_E_INVALID for a NULL plan or a bad count. */
+odf_status odf_debug_set_newton_limit(odf_plan_t *plan, int32_t max_steps);
+
 #ifdef __cplusplus
 }
 #endif

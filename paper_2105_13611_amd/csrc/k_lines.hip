@@ -79,7 +79,6 @@ hipError_t launch_prep_lines(hipStream_t st, int64_t n, const double* lam_nm, co
 // capped at fully ionised hydrogen), neutral densities consistent with it.
 constexpr double kChiH = 13.598434599702;   // eV, H I
 constexpr double kU_HI = 2.0, kU_HII = 1.0;
-constexpr int kNeMaxIter = 100;
 constexpr double kNeTol = 1e-4;
 
 // Butterfly reductions over the 64 lanes: every lane ends with the same
@@ -162,7 +161,7 @@ __device__ double equilibrium_ne(const Params& P, const Batch& B, int p, double 
   }
   int it = 0;
   bool done = false;
-  while (it < kNeMaxIter && !done) {
+  while (it < P.ne_max_iter && !done) {
     ++it;
     const double inv = 1.0 / ne;
     const ElemGQ h = elem_gq(&phiH, 2, inv);

@@ -177,6 +177,7 @@ struct Params {
   int32_t precision;       // 0 fp64, 1 mixed
   int32_t output;          // 0 ODF table, 1 fine-grid opacity
   int32_t electrons;       // 0 fixed P_e / P, 1 ionisation equilibrium
+  int32_t ne_max_iter;     // Newton steps allowed to the ionisation equilibrium
 };
 
 // ---- launchers (defined in the .hip files) ---------------------------------

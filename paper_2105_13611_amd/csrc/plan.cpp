@@ -584,6 +584,7 @@ odf_status odf_plan(const odf_lines* lines, const odf_species* species, const od
     P.precision = p->opts.precision == ODF_PREC_MIXED ? 1 : 0;
     P.output = p->opts.output == ODF_OUT_FINE ? 1 : 0;
     P.electrons = p->opts.electrons == ODF_NE_EQUILIBRIUM ? 1 : 0;
+    P.ne_max_iter = kNeMaxSteps;
   }
   p->quad = make_quad_consts();
   {
@@ -865,6 +866,16 @@ odf_status odf_stage_lines(odf_plan_t* p, const odf_request* r, int32_t point, i
     a[i] = h[i].y;
     b[i] = p->lnq / h[i].c1;
   }
+  return ODF_OK;
+}
+
+odf_status odf_debug_set_newton_limit(odf_plan_t* p, int32_t max_steps) {
+  g_err.clear();
+  if (!p) { set_error("plan is NULL"); return ODF_E_INVALID; }
+  if (max_steps < 1 || max_steps > 1000) { set_error("max_steps must be in [1, 1000]"); return ODF_E_INVALID; }
+  std::lock_guard<std::mutex> guard(p->compute_mu);
+  WorkspaceLease lease(p->loop.get());
+  p->params.ne_max_iter = max_steps;
   return ODF_OK;
 }
 

@@ -33,6 +33,9 @@ struct SlotLayout {
 // Slots of the odf_compute pipeline (at most).
 constexpr int kPipeSlots = 4;
 
+// Newton steps allowed to the ionisation equilibrium of a point.
+constexpr int kNeMaxSteps = 100;
+
 // HIP-event timing of the kernels that odf_compute launches (opt-in).
 constexpr int kStages = 6;
 struct StageTimer {

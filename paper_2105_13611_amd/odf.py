@@ -92,6 +92,7 @@ SIGNATURES = {
     "odf_stage_fine": (C.c_int, [C.c_void_p, C.POINTER(OdfRequest), C.c_int32, C.c_void_p]),
     "odf_stage_reduce": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "odf_debug_fail_next_batch": (C.c_int, [C.c_void_p, C.c_int64]),
+    "odf_debug_set_newton_limit": (C.c_int, [C.c_void_p, C.c_int32]),
     "odf_stage_times": (C.c_int, [C.c_void_p, _D, _D, _I64, C.c_int32]),
 }
 
@@ -319,6 +320,9 @@ class Plan:
 
     def fail_next_batch(self, ticket):
         _check(lib().odf_debug_fail_next_batch(self.handle, int(ticket)))
+
+    def set_newton_limit(self, max_steps):
+        _check(lib().odf_debug_set_newton_limit(self.handle, int(max_steps)))
 
     def _check_out(self, out, n_points):
         t = self.torch

@@ -110,3 +110,4 @@ def test_null_arguments(lib):
     assert lib.odf_poll(None, 1, None) == odf.ODF_E_INVALID
     assert lib.odf_point_footprint(None) == -1
     assert lib.odf_stage_state(None, None, 0, None, None) == odf.ODF_E_INVALID
+    assert lib.odf_debug_set_newton_limit(None, 5) == odf.ODF_E_INVALID

@@ -152,3 +152,28 @@ def test_equilibrium_end_to_end(odf, prec):
           f"skipped {skipped}, survivors {st['survivors']}")
     assert skipped <= 2
     assert worst <= TOL_STEP[prec]
+
+
+def test_equilibrium_failure_is_reported(odf):
+    # a Newton limit of one step, set from the host, makes these points fail
+    # to converge: odf_compute reports it, the request loop fails the ticket,
+    # and the plan works again once the limit is restored
+    w = W.config(2, n_lines=2000, lam_range=(300.0, 302.0), n_bins=2, n_requests=1)
+    w = replace(w, options=replace(w.options, electrons="equilibrium"))
+    pts = W.small_points([6000.0, 9000.0], [2.0, 4.0], [2.0, 2.0])
+    sp = w.species
+    for T, lp in zip(pts.T_K, pts.log10_P):
+        assert oracle.ionisation_equilibrium(T, lp, sp.abundance, sp.chi_ev, sp.part_fn)["iterations"] >= 3
+    with odf.plan_for(w, precision="mixed", workspace_bytes=64 << 20) as plan:
+        ok, _ = plan.compute(sp.abundance, pts)
+        plan.set_newton_limit(1)
+        with pytest.raises(odf.OdfError) as e:
+            plan.compute(sp.abundance, pts)
+        assert e.value.code == odf.ODF_E_INTERNAL and "did not converge" in str(e.value)
+        t, _ = plan.submit(sp.abundance, pts)
+        st = plan.wait(t)
+        assert st["state"] == "FAILED" and "did not converge" in st["msg"]
+        assert plan.stage_state(sp.abundance, pts, 0)["iterations"] == -1
+        plan.set_newton_limit(100)
+        again, _ = plan.compute(sp.abundance, pts)
+        assert bool((again == ok).all())
