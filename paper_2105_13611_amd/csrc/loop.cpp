@@ -29,12 +29,12 @@ RequestLoop::~RequestLoop() {
   {
     std::unique_lock<std::mutex> lk(mu_);
     stop_ = true;
-    for (auto& r : queue_) {
+    for (auto& r : sched_.waiting()) {
       r->stats.state = ODF_FAILED;
       r->stats.t_done = now();
       std::snprintf(r->stats.msg, sizeof r->stats.msg, "cancelled: plan destroyed before admission");
     }
-    queue_.clear();
+    sched_.waiting().clear();
     cv_.notify_all();
   }
   if (th_.joinable()) th_.join();
@@ -110,7 +110,7 @@ odf_status RequestLoop::submit(const odf_request* r, int64_t* ticket) {
   q->id = next_id_++;
   q->stats.t_submit = now();
   all_[q->id] = q;
-  queue_.push_back(q);
+  sched_.enqueue(q);
   *ticket = q->id;
   cv_.notify_all();
   return ODF_OK;
@@ -241,7 +241,7 @@ void RequestLoop::finish_locked(Slot& s, bool ok, const char* msg) {
   if (final_failed || final_done) {
     r->stats.state = final_done ? ODF_DONE : ODF_FAILED;
     r->stats.t_done = now();
-    active_.erase(std::remove(active_.begin(), active_.end(), r), active_.end());
+    sched_.retire(r);
   }
   cv_.notify_all();
 }
@@ -275,36 +275,22 @@ void RequestLoop::run() {
       }
     }
     if (!exclusive_) {
-      while (!queue_.empty() && (int32_t)active_.size() < max_active_) {
-        auto r = queue_.front();
-        queue_.pop_front();
-        if (r->n_points == 0) {
-          r->stats.state = ODF_DONE;
-          r->stats.t_admit = r->stats.t_done = now();
-          cv_.notify_all();
-          continue;
-        }
-        active_.push_back(r);
+      if (sched_.admit([&](const std::shared_ptr<Request>& r) {
+            r->stats.state = ODF_DONE;
+            r->stats.t_admit = r->stats.t_done = now();
+            cv_.notify_all();
+          }))
         progress = true;
-      }
       for (auto& s : slots_) {
-        if (s.busy || active_.empty()) continue;
-        std::shared_ptr<Request> pick;
-        for (size_t k = 0; k < active_.size(); ++k) {
-          auto& c = active_[(rr_ + k) % active_.size()];
-          if (!c->failed && c->next < c->n_points) {
-            pick = c;
-            rr_ = (rr_ + k + 1) % std::max<size_t>(active_.size(), 1);
-            break;
-          }
-        }
+        if (s.busy) continue;
+        std::shared_ptr<Request> pick = sched_.pick();
         if (!pick) break;
         dispatch_locked(s, pick);
         if (s.busy) any_busy = true;
         progress = true;
       }
     }
-    if (stop_ && queue_.empty() && active_.empty() && !any_busy) break;
+    if (stop_ && sched_.idle() && !any_busy) break;
     if (!progress) {
       if (!any_busy) {
         cv_.wait(lk);

@@ -12,6 +12,7 @@
 #pragma once
 
 #include "plan.h"
+#include "scheduler.h"
 
 namespace odf {
 
@@ -81,12 +82,9 @@ class RequestLoop {
   std::vector<hipStream_t> streams_;
   std::mutex mu_;
   std::condition_variable cv_;
-  std::deque<std::shared_ptr<Request>> queue_;        // waiting for admission
-  std::vector<std::shared_ptr<Request>> active_;      // admitted, not final
+  BatchScheduler<Request> sched_{16};                // admission and batch hand-out
   std::map<int64_t, std::shared_ptr<Request>> all_;   // every ticket
   int64_t next_id_ = 1;
-  size_t rr_ = 0;
-  int32_t max_active_ = 16;
   bool stop_ = false;
   bool started_ = false;
   bool start_failed_ = false;
