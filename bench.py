@@ -49,8 +49,9 @@ WORKLOADS = {
 
 # nominal FP32 operations per Voigt sample on the far-wing path (the path
 # almost every sample takes), FMA = 2: u carried from the previous row 2,
-# u from the index at the first of eight rows 6/8, u^2 1, numerator 2,
-# denominator 3, reciprocal 1, accumulate 2, compensated add every 64 lines 4/64
+# u from the index at the first of eight rows 6/8, v = u^2 + D 2, numerator
+# 2, denominator 2, reciprocal 1, accumulate 2, compensated add every 64
+# lines 4/64
 FLOP_PER_SAMPLE_F32 = 11.8
 # FP64 far wing (four-node pair as one fraction in X = x^2): x carried 2,
 # X 1, numerator and denominator Horner chains 14, reciprocal with one Newton

@@ -588,16 +588,16 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
       if (e.a >= 1.0e4) {
         // Lorentz limit in u = x / a
         r.c1 = (float)(c1 / e.a);
-        r.A = r.B = (float)(C1 / (e.a * e.a));
-        r.K1 = 2.0f;
-        r.K2 = 1.0f;
+        r.A = (float)(C1 / (e.a * e.a));
+        r.B = 0.0f;
+        r.D = 1.0f;
+        r.E = 0.0f;
       } else {
-        const double C2 = e.a * e.a + 0.5;   // t^2 = 1/2 for the two-node rule
+        // two-node rule (t^2 = 1/2)
         r.c1 = (float)c1;
-        r.A = (float)C1;
-        r.B = (float)(C1 * C2);
-        r.K1 = (float)(2.0 * e.a * e.a - 1.0);
-        r.K2 = (float)(C2 * C2);
+        r.A = r.B = (float)C1;
+        r.D = (float)(e.a * e.a - 0.5);
+        r.E = (float)(2.0 * e.a * e.a);
       }
       r.S = (float)e.S;
       r.y = (float)e.a;

@@ -172,7 +172,7 @@ __device__ __forceinline__ float series32(float x, float y, float y2, float y_ov
 //   u(row + 1) = u(row) q^-64 + step  (the frequency ratio of 64 points).
 struct Far32 {
   float c1, c2, c3, step;
-  float A, B, K1, K2;
+  float A, B, D, E;
 };
 
 // Bit mask of the rows (of the wave's 16) that meet [J - half, J + half].
@@ -200,8 +200,8 @@ __device__ __forceinline__ unsigned rows_between(int a, int b) {
 }
 
 __device__ __forceinline__ float far_value(float u, const Far32& f) {
-  const float u2 = u * u;
-  return fmaf(u2, f.A, f.B) * __builtin_amdgcn_rcpf(fmaf(u2, u2 + f.K1, f.K2));
+  const float v = fmaf(u, u, f.D);
+  return fmaf(v, f.A, f.B) * __builtin_amdgcn_rcpf(fmaf(v, v, f.E));
 }
 
 __device__ __forceinline__ float x_of_d32(float d, const Far32& f) {
@@ -213,7 +213,7 @@ __device__ __forceinline__ float x_of_d32(float d, const Far32& f) {
 // Rows go in groups of eight: u is taken from the index at the start of a
 // group and carried to the next row by the exact frequency ratio q^-64 (one
 // FMA; the rounding this accumulates over seven rows stays below 1e-6 of
-// u).  A row of a group that is not in the mask gets K2 = +inf (a scalar
+// u).  A row of a group that is not in the mask gets E = +inf (a scalar
 // select), so its reciprocal is exactly zero and it adds nothing, at no extra
 // vector cost (skipping such rows with a uniform branch per row instead
 // measured 24 % slower overall); groups with no row in the mask are skipped.
@@ -231,10 +231,10 @@ __device__ __forceinline__ void rows32(unsigned rows, float d0, float q64, const
     float u = x_of_d32(d0 - (float)(64 * g), f);
 #pragma unroll
     for (int r = 0; r < kGroup; ++r) {
-      const int K2 = ((gm >> r) & 1u) ? __float_as_int(f.K2) : inf;   // uniform
-      const float u2 = u * u;
-      const float den = fmaf(u2, u2 + f.K1, __int_as_float(K2));
-      p[g + r] = fmaf(fmaf(u2, f.A, f.B), __builtin_amdgcn_rcpf(den), p[g + r]);
+      const int E = ((gm >> r) & 1u) ? __float_as_int(f.E) : inf;   // uniform
+      const float v = fmaf(u, u, f.D);
+      const float den = fmaf(v, v, __int_as_float(E));
+      p[g + r] = fmaf(fmaf(v, f.A, f.B), __builtin_amdgcn_rcpf(den), p[g + r]);
       u = fmaf(u, q64, f.step);
     }
   }
@@ -251,8 +251,8 @@ __device__ __forceinline__ void line32(const Rec32& l, int t_lo, int t_hi, int l
   f.step = g64 * l.c1;
   f.A = l.A;
   f.B = l.B;
-  f.K1 = l.K1;
-  f.K2 = l.K2;
+  f.D = l.D;
+  f.E = l.E;
   const int rel = l.J - t_lo;
   const int ib = rel - lane;
   const float d0 = (float)ib + l.phi;
@@ -335,8 +335,8 @@ __device__ __forceinline__ Rec32 load_rec32(const Rec32* __restrict__ p) {
   r.c1 = __int_as_float(b.y);
   r.A = __int_as_float(b.z);
   r.B = __int_as_float(b.w);
-  r.K1 = __int_as_float(c.x);
-  r.K2 = __int_as_float(c.y);
+  r.D = __int_as_float(c.x);
+  r.E = __int_as_float(c.y);
   r.S = __int_as_float(c.z);
   r.y = __int_as_float(c.w);
   return r;

@@ -110,20 +110,24 @@ struct PointState {
 // scalar loads.  `czh` is the half-width in fine points of the zone around
 // the centre where |x + i a| may be below the far-wing radius (-1: none).
 //
-// FP32 far wing: S H = (A u^2 + B) / (u^2 (u^2 + K1) + K2), u = sigma x,
-//  - two-node Gauss-Hermite pair (a < 1e4), sigma = 1, C1 = S a / sqrt(pi),
-//    C2 = a^2 + 1/2: A = C1, B = C1 C2, K1 = 2 a^2 - 1, K2 = C2^2;
+// FP32 far wing: S H = (A v + B) / (v^2 + E), v = u^2 + D, u = sigma x,
+//  - two-node Gauss-Hermite pair (a < 1e4), sigma = 1, C1 = S a / sqrt(pi):
+//    the pair's fraction C1 (u^2 + a^2 + 1/2) / ((u^2 + a^2 - 1/2)^2 + 2 a^2),
+//    so A = B = C1, D = a^2 - 1/2, E = 2 a^2;
 //  - Lorentz limit (a >= 1e4, pair correction below 1/(2 a^2)), sigma = 1/a:
-//    A = B = C1 / a^2, K1 = 2, K2 = 1, i.e. C1 / (x^2 + a^2) without
-//    overflow at any a.
-// sigma is folded into c1, so the kernel computes u directly from the index.
+//    C1 / (x^2 + a^2) = (C1 / a^2) / (u^2 + 1), so A = C1 / a^2, B = 0,
+//    D = 1, E = 0, without overflow at any a.
+// In the far wing v >= 224, so writing the denominator as a square plus E
+// loses nothing, and a row costs one FMA for v, one for the denominator and
+// one for the numerator.  sigma is folded into c1, so the kernel computes u
+// directly from the index.
 struct alignas(16) Rec32 {
   int32_t J;        // nearest integer of the fractional centre index
   int32_t jlo, jhi; // window, clipped to the grid
   int32_t czh;      // zone half-widths: low 16 bits |x| < 15, high 16 bits |x| < 6 (-32768: none)
   float phi;        // fractional centre minus J, in [-1/2, 1/2]
   float c1;         // sigma ln q / b, so u ~= d c1 (1 + d ln q / 2 + ...)
-  float A, B, K1, K2;   // far-wing fraction (above)
+  float A, B, D, E;     // far-wing fraction (above)
   float S;          // line strength
   float y;          // damping parameter a
 };
