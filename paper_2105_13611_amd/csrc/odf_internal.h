@@ -39,9 +39,10 @@ constexpr int kTrap32Half = 6;                   // k = -6..6
 constexpr float kTrap32H = 0.75f;
 constexpr float kTrap32Tmax = 4.2f;
 // FP64: rows with all |x| >= 40 -> four-node Gauss-Hermite pair sum (relative
-// error below 3e-12); all |x| >= 10 -> eight-node (below 5e-13); other rows ->
-// trapezoid h = 0.55, nodes |t| <= 5.9 (below 1.2e-13), for every lane.
-constexpr double kFarR64 = 10.0;
+// error below 3e-12); all |x| >= 8 -> eight-node (below 2e-11, 4e-13 from
+// |x| = 10 on); other rows -> trapezoid h = 0.55, nodes |t| <= 5.9 (below
+// 1.2e-13), for every lane.
+constexpr double kFarR64 = 8.0;
 constexpr double kFar4R64 = 40.0;
 constexpr int kTrap64Half = 11;                  // k = -11..11
 constexpr double kTrap64H = 0.55;
@@ -133,7 +134,7 @@ struct alignas(16) Rec32 {
 };
 struct alignas(16) Rec64 {
   int32_t J, jlo, jhi;
-  int32_t czh;      // half-width of the zone where |x| < 10 may occur (-1: none)
+  int32_t czh;      // half-width of the zone where |x| < 8 may occur (-1: none)
   int32_t z40;      // the same for |x| < 40
   int32_t li;       // sorted line index (stage checks)
   int32_t pad0, pad1;
