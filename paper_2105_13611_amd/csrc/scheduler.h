@@ -62,10 +62,14 @@ class BatchScheduler {
   }
 
   // A request that reached its final state leaves the resident set.
+  // The turn stays with the request that was next.
   void retire(const std::shared_ptr<R>& r) {
-    active_.erase(std::remove(active_.begin(), active_.end(), r), active_.end());
-    if (!active_.empty()) rr_ %= active_.size();
-    else rr_ = 0;
+    const auto it = std::find(active_.begin(), active_.end(), r);
+    if (it == active_.end()) return;
+    const size_t i = (size_t)(it - active_.begin());
+    active_.erase(it);
+    if (i < rr_) --rr_;
+    if (rr_ >= active_.size()) rr_ = 0;
   }
 
   bool idle() const { return queue_.empty() && active_.empty(); }

@@ -93,6 +93,24 @@ int main() {
     s.retire(r[0]);
     CHECK(serve(s, 1) == 2 && serve(s, 1) == 2);
   }
+  {  // retiring a request served earlier keeps the turn with the next one
+    odf::BatchScheduler<Req> s(4);
+    std::vector<P> r;
+    for (int i = 0; i < 3; ++i) {
+      r.push_back(std::make_shared<Req>(i, 100));
+      s.enqueue(r.back());
+    }
+    s.admit([&](const P&) {});
+    CHECK(serve(s, 1) == 0);
+    CHECK(serve(s, 1) == 1);
+    s.retire(r[0]);                  // request 2 was next
+    CHECK(serve(s, 1) == 2);
+    CHECK(serve(s, 1) == 1);
+    s.retire(r[2]);                  // retiring the one just served
+    CHECK(serve(s, 1) == 1);
+    s.retire(r[0]);                  // not resident: no effect
+    CHECK(s.resident() == 1);
+  }
   {  // fairness: three long requests share the slots evenly
     odf::BatchScheduler<Req> s(16);
     std::vector<P> r;
