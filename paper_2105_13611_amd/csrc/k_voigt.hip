@@ -240,8 +240,22 @@ __device__ __forceinline__ void rows32(unsigned rows, float d0, float q64, const
   }
 }
 
-__device__ __forceinline__ void line32(const Rec32& l, int t_lo, int t_hi, int lane, float lnq2,
-                                       float lnq6, float q64, float g64,
+// The window's rows of the tile and the window-edge rows of 64 records at
+// once, one record per lane (0 <= jl <= jh <= 1023 for records that meet the
+// tile; other lanes compute values nobody reads): rows in the low 16 bits,
+// edges in the high 16.  One vector pass per batch of records replaces the
+// scalar work each line would otherwise do.
+__device__ __forceinline__ unsigned window_rows(int2 w, int t_lo, int t_hi) {
+  const int jl = max(w.x, t_lo) - t_lo;
+  const int jh = min(w.y, t_hi) - t_lo;
+  const int r_lo = (jl >> 6) & 31, r_hi = (jh >> 6) & 31;
+  const unsigned rows = (0xffffu << r_lo) & (0xffffu >> ((kRows - 1 - r_hi) & 31));
+  const unsigned edge = ((jl & 63) ? (1u << r_lo) : 0u) | ((jh & 63) != 63 ? (1u << r_hi) : 0u);
+  return rows | (edge << 16);
+}
+
+__device__ __forceinline__ void line32(const Rec32& l, unsigned rows_edge, int t_lo, int lane,
+                                       float lnq2, float lnq6, float q64, float g64,
                                        const QuadConsts* __restrict__ Q, const float4* __restrict__ tab,
                                        float (&p)[kRows], float* __restrict__ lp) {
   Far32 f;
@@ -260,14 +274,10 @@ __device__ __forceinline__ void line32(const Rec32& l, int t_lo, int t_hi, int l
   const int zfar = (int)(short)(l.czh & 0xffff);   // |x| < 15
   const int zring = l.czh >> 16;                   // |x| < 6
   const unsigned near = rows_between(rel - zfar, rel + zfar);
-  const int jl = max(l.jlo, t_lo) - t_lo;
-  const int jh = min(l.jhi, t_hi) - t_lo;
-  const int r_lo = jl >> 6, r_hi = jh >> 6;   // 0 <= jl <= jh <= 1023 here
-  const unsigned rows = (0xffffu << r_lo) & (0xffffu >> (kRows - 1 - r_hi));
   // rows cut by the window edge (at most two): the window starts inside its
   // first row or ends inside its last; lanes past the grid's end are summed
   // like the others and never stored
-  const unsigned edge = ((jl & 63) ? (1u << r_lo) : 0u) | ((jh & 63) != 63 ? (1u << r_hi) : 0u);
+  const unsigned rows = rows_edge & 0xffffu, edge = rows_edge >> 16;
   const unsigned nearr = near & rows;
   // kept in a scalar register, so that the masks stay scalar operations
   unsigned ne = near | edge;
@@ -394,7 +404,7 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
   // lane, the next 64 prefetched while these are summed; each intersecting
   // record is then read with scalar loads
   // (lanes past the end hold an empty window that meets no tile)
-  const int2 none = make_int2(0x7fffffff, -0x7fffffff - 1);
+  const int2 none = make_int2(0x3fffffff, -0x3fffffff);
   int2 nxt = none;
   if (c0 + lane < c1) nxt = win[c0 + lane];
   for (int base = c0; base < c1; base += 64) {
@@ -402,10 +412,13 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
     nxt = none;
     if (base + 64 + lane < c1) nxt = win[base + 64 + lane];
     unsigned long long m = __ballot(cur.x <= t_hi && cur.y >= t_lo);
+    if (!m) continue;
+    const unsigned re = window_rows(cur, t_lo, t_hi);
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(m));
       m &= m - 1;
-      line32(load_rec32(rec + base + k), t_lo, t_hi, lane, lnq2, lnq6, q64, g64, Q, lds_ser, p, lp);
+      line32(load_rec32(rec + base + k), __builtin_amdgcn_readlane(re, k), t_lo, lane, lnq2, lnq6,
+             q64, g64, Q, lds_ser, p, lp);
       if (++since_flush == kFlushLines) {
         flush32(s, p, lp, lc, lane);
         since_flush = 0;
