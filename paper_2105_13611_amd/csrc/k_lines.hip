@@ -562,6 +562,7 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
       const int32_t far = e.a < kFarR32 ? min(zone_half(kFarR32, c1), 32767) : -32768;
       const int32_t ring = e.a < kRingR32 ? min(zone_half(kRingR32, c1), 32767) : -32768;
       czh = (int32_t)(((uint32_t)ring << 16) | ((uint32_t)far & 0xffffu));
+      B.wz[slot] = make_int2(J, czh);
     }
     if (kRec64) {
       Rec64 r;

@@ -184,21 +184,6 @@ __device__ __forceinline__ unsigned zone_rows(int J, int half, int t_lo) {
   return ((2u << hi) - 1u) & ~((1u << lo) - 1u);
 }
 
-// Bit mask of the rows (of the wave's 16) that meet [a, b], both relative to
-// the tile's first point, uniform and of any sign; empty when b < a by 64 or
-// more or when the interval misses the tile.  Branch-free scalar arithmetic
-// (the empty asm keeps each clamp a pair of scalar min/max instead of a
-// vector three-operand clamp read back into scalar registers).
-__device__ __forceinline__ unsigned rows_between(int a, int b) {
-  int lo = max(a >> 6, 0);
-  asm("" : "+s"(lo));
-  lo = min(lo, kRows);
-  int hi = max(b >> 6, -1);
-  asm("" : "+s"(hi));
-  hi = min(hi, kRows - 1);
-  return (0xffffu << lo) & (0xffffu >> (kRows - 1 - hi));
-}
-
 __device__ __forceinline__ float far_value(float u, const Far32& f) {
   const float v = fmaf(u, u, f.D);
   return fmaf(v, f.A, f.B) * __builtin_amdgcn_rcpf(fmaf(v, v, f.E));
@@ -240,21 +225,39 @@ __device__ __forceinline__ void rows32(unsigned rows, float d0, float q64, const
   }
 }
 
-// The window's rows of the tile and the window-edge rows of 64 records at
-// once, one record per lane (0 <= jl <= jh <= 1023 for records that meet the
-// tile; other lanes compute values nobody reads): rows in the low 16 bits,
-// edges in the high 16.  One vector pass per batch of records replaces the
-// scalar work each line would otherwise do.
-__device__ __forceinline__ unsigned window_rows(int2 w, int t_lo, int t_hi) {
+// Row masks of 64 records at once, one record per lane, on the vector unit
+// (one pass per batch of records instead of scalar work per line and wave):
+//   rows  the tile's rows that the window meets
+//   edge  rows cut by the window edge (it starts inside its first row or
+//         ends inside its last)
+//   near  rows meeting the |x| < 15 zone, core rows meeting |x| < 6
+// Packed as far | (masked << 16) and near_in_window | (core << 16), where far
+// are the rows summed in registers and masked those summed lane by lane.
+// For records that meet the tile 0 <= jl <= jh <= 1023; the other lanes
+// compute values that nobody reads.  A zone half-width of -32768 gives no
+// rows.
+__device__ __forceinline__ unsigned zone_rows_v(int rel, int z) {
+  const int lo = min(max((rel - z) >> 6, 0), kRows);
+  const int hi = min(max((rel + z) >> 6, -1), kRows - 1);
+  return (0xffffu << lo) & (0xffffu >> (kRows - 1 - hi));
+}
+
+__device__ __forceinline__ void row_masks(int2 w, int2 jz, int t_lo, int t_hi, unsigned& fm,
+                                          unsigned& nc) {
   const int jl = max(w.x, t_lo) - t_lo;
   const int jh = min(w.y, t_hi) - t_lo;
   const int r_lo = (jl >> 6) & 31, r_hi = (jh >> 6) & 31;
   const unsigned rows = (0xffffu << r_lo) & (0xffffu >> ((kRows - 1 - r_hi) & 31));
   const unsigned edge = ((jl & 63) ? (1u << r_lo) : 0u) | ((jh & 63) != 63 ? (1u << r_hi) : 0u);
-  return rows | (edge << 16);
+  const int rel = jz.x - t_lo;
+  const unsigned near = zone_rows_v(rel, (int)(short)(jz.y & 0xffff));
+  const unsigned core = zone_rows_v(rel, jz.y >> 16);
+  fm = (rows & ~(near | edge)) | (((near | edge) & rows) << 16);
+  nc = (near & rows) | (core << 16);
 }
 
-__device__ __forceinline__ void line32(const Rec32& l, unsigned rows_edge, int t_lo, int lane,
+__device__ __forceinline__ void line32(const Rec32& l, unsigned far_masked, unsigned near_core,
+                                       int t_lo, int lane,
                                        float lnq2, float lnq6, float q64, float g64,
                                        const QuadConsts* __restrict__ Q, const float4* __restrict__ tab,
                                        float (&p)[kRows], float* __restrict__ lp) {
@@ -270,24 +273,15 @@ __device__ __forceinline__ void line32(const Rec32& l, unsigned rows_edge, int t
   const int rel = l.J - t_lo;
   const int ib = rel - lane;
   const float d0 = (float)ib + l.phi;
-  // zone half-widths (a sentinel of -32768 makes a zone empty)
-  const int zfar = (int)(short)(l.czh & 0xffff);   // |x| < 15
-  const int zring = l.czh >> 16;                   // |x| < 6
-  const unsigned near = rows_between(rel - zfar, rel + zfar);
-  // rows cut by the window edge (at most two): the window starts inside its
-  // first row or ends inside its last; lanes past the grid's end are summed
-  // like the others and never stored
-  const unsigned rows = rows_edge & 0xffffu, edge = rows_edge >> 16;
-  const unsigned nearr = near & rows;
-  // kept in a scalar register, so that the masks stay scalar operations
-  unsigned ne = near | edge;
-  asm("" : "+s"(ne));
-  rows32(rows & ~ne, d0, q64, f, p);
-  unsigned m = (nearr | edge) & rows;
+  // far rows in registers; edge rows and rows near the core lane by lane
+  // (lanes past the grid's end are summed like the others and never stored)
+  rows32(far_masked & 0xffffu, d0, q64, f, p);
+  unsigned m = far_masked >> 16;
   if (!m) return;
-  // edge rows and rows near the core: per-lane masks, partial sums in LDS
-  // (near rows exist only for a < 15, where sigma = 1 and u = x)
-  const unsigned core = rows_between(rel - zring, rel + zring);
+  // per-lane masks, partial sums in LDS (near rows exist only for a < 15,
+  // where sigma = 1 and u = x)
+  const unsigned nearr = near_core & 0xffffu;   // rows meeting |x| < 15
+  const unsigned core = near_core >> 16;        // rows meeting |x| < 6
   const float y = l.y, S = l.S;
   const float y2 = y * y;
   const bool ser = y < kSerYMax;
@@ -391,6 +385,7 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
   }
   const Rec32* __restrict__ rec = reinterpret_cast<const Rec32*>(B.rec) + pt * B.rec_stride;
   const int2* __restrict__ win = B.win + pt * B.rec_stride;
+  const int2* __restrict__ wz = B.wz + pt * B.rec_stride;
   const int ns = B.nsurv[pt];
   const int H = B.hmax[pt];
   const float lnq = (float)P.lnq;
@@ -405,20 +400,27 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
   // record is then read with scalar loads
   // (lanes past the end hold an empty window that meets no tile)
   const int2 none = make_int2(0x3fffffff, -0x3fffffff);
-  int2 nxt = none;
-  if (c0 + lane < c1) nxt = win[c0 + lane];
+  int2 nxt = none, nxz = make_int2(0, 0);
+  if (c0 + lane < c1) {
+    nxt = win[c0 + lane];
+    nxz = wz[c0 + lane];
+  }
   for (int base = c0; base < c1; base += 64) {
-    const int2 cur = nxt;
+    const int2 cur = nxt, cz = nxz;
     nxt = none;
-    if (base + 64 + lane < c1) nxt = win[base + 64 + lane];
+    if (base + 64 + lane < c1) {
+      nxt = win[base + 64 + lane];
+      nxz = wz[base + 64 + lane];
+    }
     unsigned long long m = __ballot(cur.x <= t_hi && cur.y >= t_lo);
     if (!m) continue;
-    const unsigned re = window_rows(cur, t_lo, t_hi);
+    unsigned fm, nc;
+    row_masks(cur, cz, t_lo, t_hi, fm, nc);
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(m));
       m &= m - 1;
-      line32(load_rec32(rec + base + k), __builtin_amdgcn_readlane(re, k), t_lo, lane, lnq2, lnq6,
-             q64, g64, Q, lds_ser, p, lp);
+      line32(load_rec32(rec + base + k), __builtin_amdgcn_readlane(fm, k),
+             __builtin_amdgcn_readlane(nc, k), t_lo, lane, lnq2, lnq6, q64, g64, Q, lds_ser, p, lp);
       if (++since_flush == kFlushLines) {
         flush32(s, p, lp, lc, lane);
         since_flush = 0;

@@ -159,6 +159,7 @@ struct Batch {
   int32_t* nit;         // [B]         ionisation-equilibrium steps (0: fixed P_e; < 0: not converged)
   void* rec;            // [B][L] Rec32 or Rec64
   int2* win;            // [B][L] (jlo, jhi) of each record, scanned by the Voigt kernels
+  int2* wz;             // [B][L] (J, czh) of each FP32 record, read with its window (mixed plans)
   void* kappa;          // [B][N] float or double
   int64_t rec_stride;   // = L
   int64_t kappa_stride; // = N

@@ -223,6 +223,7 @@ SlotLayout make_slot(const odf_plan_s* p, int32_t pts) {
   s.off_nit = take(4 * pts);
   s.off_rec = take((mixed ? (int64_t)sizeof(Rec32) : (int64_t)sizeof(Rec64)) * std::max<int64_t>(L, 1) * pts);
   s.off_win = take((int64_t)sizeof(int2) * std::max<int64_t>(L, 1) * pts);
+  s.off_wz = take(mixed ? (int64_t)sizeof(int2) * std::max<int64_t>(L, 1) * pts : 0);
   s.off_kappa = take((mixed ? 4 : 8) * p->N * pts);
   s.off_gscr = take((mixed ? 4 : 8) * std::max<int64_t>(p->gscr_elems, 1) * pts);
   s.bytes = o;
@@ -248,6 +249,7 @@ Batch make_batch(const odf_plan_s* p, const SlotLayout& s, char* base, int32_t n
   B.nit = reinterpret_cast<int32_t*>(base + s.off_nit);
   B.rec = base + s.off_rec;
   B.win = reinterpret_cast<int2*>(base + s.off_win);
+  B.wz = reinterpret_cast<int2*>(base + s.off_wz);
   B.kappa = base + s.off_kappa;
   B.rec_stride = std::max<int64_t>(p->n_lines, 1);
   B.kappa_stride = p->N;
