@@ -106,10 +106,12 @@ struct PointState {
 };
 
 // Survivor records, one per kept line and point, in wavelength order.  A
-// wave loads the windows of 64 of them at a time (one per lane), tests them
-// against its tile with one ballot and reads each intersecting record with
-// scalar loads.  `czh` is the half-width in fine points of the zone around
-// the centre where |x + i a| may be below the far-wing radius (-1: none).
+// wave loads the windows of 64 of them at a time (one per lane; for FP32
+// records also their (J, czh), from which each lane computes its record's
+// row masks), tests them against its tile with one ballot and reads each
+// intersecting record with scalar loads.  `czh` holds the half-widths in fine
+// points of the zones around the centre where |x + i a| may be below the
+// rules' radii (FP32: two 16-bit fields, -32768 for none; FP64: -1 for none).
 //
 // FP32 far wing: S H = (A v + B) / (v^2 + E), v = u^2 + D, u = sigma x,
 //  - two-node Gauss-Hermite pair (a < 1e4), sigma = 1, C1 = S a / sqrt(pi):
