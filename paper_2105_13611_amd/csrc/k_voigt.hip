@@ -184,6 +184,12 @@ __device__ __forceinline__ unsigned zone_rows(int J, int half, int t_lo) {
   return ((2u << hi) - 1u) & ~((1u << lo) - 1u);
 }
 
+// The wave's 16 row partial sums as one vector of registers.  Rows summed
+// lane by lane are picked by a uniform runtime index, which indexes the
+// register file directly (no LDS round trip per row, no LDS array for it).
+typedef float RowVec __attribute__((ext_vector_type(kRows)));
+static_assert(kRows == 16, "row partial sums are a 16-wide register vector");
+
 __device__ __forceinline__ float far_value(float u, const Far32& f) {
   const float v = fmaf(u, u, f.D);
   return fmaf(v, f.A, f.B) * __builtin_amdgcn_rcpf(fmaf(v, v, f.E));
@@ -202,11 +208,8 @@ __device__ __forceinline__ float x_of_d32(float d, const Far32& f) {
 // select), so its reciprocal is exactly zero and it adds nothing, at no extra
 // vector cost (skipping such rows with a uniform branch per row instead
 // measured 24 % slower overall); groups with no row in the mask are skipped.
-// This is the only
-// place that updates the register sums, so they stay in one set of
-// registers.
 __device__ __forceinline__ void rows32(unsigned rows, float d0, float q64, const Far32& f,
-                                       float (&p)[kRows]) {
+                                       RowVec& p) {
   constexpr int kGroup = 8;
   const int inf = 0x7f800000;
 #pragma unroll
@@ -260,7 +263,7 @@ __device__ __forceinline__ void line32(const Rec32& l, unsigned far_masked, unsi
                                        int t_lo, int lane,
                                        float lnq2, float lnq6, float q64, float g64,
                                        const QuadConsts* __restrict__ Q, const float4* __restrict__ tab,
-                                       float (&p)[kRows], float* __restrict__ lp) {
+                                       RowVec& p) {
   Far32 f;
   f.c1 = l.c1;
   f.c2 = l.c1 * lnq2;
@@ -278,8 +281,8 @@ __device__ __forceinline__ void line32(const Rec32& l, unsigned far_masked, unsi
   rows32(far_masked & 0xffffu, d0, q64, f, p);
   unsigned m = far_masked >> 16;
   if (!m) return;
-  // per-lane masks, partial sums in LDS (near rows exist only for a < 15,
-  // where sigma = 1 and u = x)
+  // per-lane masks, into the same register partial sums, row picked by its
+  // index (near rows exist only for a < 15, where sigma = 1 and u = x)
   const unsigned nearr = near_core & 0xffffu;   // rows meeting |x| < 15
   const unsigned core = near_core >> 16;        // rows meeting |x| < 6
   const float y = l.y, S = l.S;
@@ -301,21 +304,20 @@ __device__ __forceinline__ void line32(const Rec32& l, unsigned far_masked, unsi
     }
     const int j = t_lo + 64 * rr + lane;
     v = (j >= l.jlo && j <= l.jhi) ? v : 0.0f;
-    lp[rr * 64 + lane] += v;
+    p[rr] += v;
   }
 }
 
 // Compensated (Kahan) addition of the partial sums into the row sums: the
 // running sums s stay in registers, their compensations c in LDS.
-__device__ __forceinline__ void flush32(float (&s)[kRows], float (&p)[kRows],
-                                        float* __restrict__ lp, float* __restrict__ lc, int lane) {
+__device__ __forceinline__ void flush32(float (&s)[kRows], RowVec& p, float* __restrict__ lc,
+                                        int lane) {
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) {
     const int o = rr * 64 + lane;
     float c = lc[o];
-    kahan_add(s[rr], c, p[rr] + lp[o]);
+    kahan_add(s[rr], c, p[rr]);
     lc[o] = c;
-    lp[o] = 0.0f;
     p[rr] = 0.0f;
   }
 }
@@ -350,10 +352,12 @@ __device__ __forceinline__ Rec32 load_rec32(const Rec32* __restrict__ p) {
 // partial of at most 64 positive terms is within 64 u = 3.8e-6 of its value)
 constexpr int kFlushLines = 64;
 
-__global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
-                                                 const QuadConsts* __restrict__ Q,
-                                                 int tiles_per_point, int total) {
-  __shared__ float lds_p[kWavesPerWG][kWavePoints];   // partial sums of core/ring rows
+// Six workgroups per CU (6 waves per SIMD): at most 80 VGPRs, which the
+// register allocator meets without spilling, and 24 KB of LDS per workgroup.
+// It measured 5 % faster than the 5 waves per SIMD that 95 VGPRs give.
+__global__ __launch_bounds__(256, 6) void k_voigt32(Params P, Batch B,
+                                                    const QuadConsts* __restrict__ Q,
+                                                    int tiles_per_point, int total) {
   __shared__ float lds_c[kWavesPerWG][kWavePoints];   // Kahan compensations
   __shared__ float4 lds_ser[kSerTerms * kSerIntervals]; // small-damping series table
   const int logical = tile_order(blockIdx.x, total);
@@ -373,12 +377,11 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
   const int t_lo = tile * kWGPoints + wid * kWavePoints;
   if (t_lo >= N) return;
   const int t_hi = min(t_lo + kWavePoints - 1, N - 1);
-  float* lp = lds_p[wid];
   float* lc = lds_c[wid];
-  float s[kRows], p[kRows];
+  float s[kRows];
+  RowVec p;
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) {
-    lp[rr * 64 + lane] = 0.0f;
     lc[rr * 64 + lane] = 0.0f;
     s[rr] = 0.0f;
     p[rr] = 0.0f;
@@ -420,14 +423,14 @@ __global__ __launch_bounds__(256) void k_voigt32(Params P, Batch B,
       const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(m));
       m &= m - 1;
       line32(load_rec32(rec + base + k), __builtin_amdgcn_readlane(fm, k),
-             __builtin_amdgcn_readlane(nc, k), t_lo, lane, lnq2, lnq6, q64, g64, Q, lds_ser, p, lp);
+             __builtin_amdgcn_readlane(nc, k), t_lo, lane, lnq2, lnq6, q64, g64, Q, lds_ser, p);
       if (++since_flush == kFlushLines) {
-        flush32(s, p, lp, lc, lane);
+        flush32(s, p, lc, lane);
         since_flush = 0;
       }
     }
   }
-  flush32(s, p, lp, lc, lane);
+  flush32(s, p, lc, lane);
   float* kap = reinterpret_cast<float*>(B.kappa) + pt * B.kappa_stride;
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) {
