@@ -127,7 +127,8 @@ struct PointState {
 struct alignas(16) Rec32 {
   int32_t J;        // nearest integer of the fractional centre index
   int32_t jlo, jhi; // window, clipped to the grid
-  int32_t czh;      // zone half-widths: low 16 bits |x| < 15, high 16 bits |x| < 6 (-32768: none)
+  int32_t czh;      // zone half-widths: low 16 bits |x| < 15, high 16 bits |x| < 6 (-32768: none);
+                    // the Voigt kernel reads them from the (J, czh) array, this copy completes the record
   float phi;        // fractional centre minus J, in [-1/2, 1/2]
   float c1;         // sigma ln q / b, so u ~= d c1 (1 + d ln q / 2 + ...)
   float A, B, D, E;     // far-wing fraction (above)
