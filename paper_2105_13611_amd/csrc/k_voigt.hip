@@ -238,7 +238,10 @@ __device__ __forceinline__ void rows32(unsigned rows, float d0, float q64, const
 // are the rows summed in registers and masked those summed lane by lane.
 // For records that meet the tile 0 <= jl <= jh <= 1023; the other lanes
 // compute values that nobody reads.  A zone half-width of -32768 gives no
-// rows.
+// rows.  A record whose window covers the tile, whose |x| < 15 zone misses
+// it and whose centre lies more than kFFDist points outside the tile's 1024
+// points is a far-field record: fm = nc = 0 (any other record that meets
+// the tile has a row in fm).
 __device__ __forceinline__ unsigned zone_rows_v(int rel, int z) {
   const int lo = min(max((rel - z) >> 6, 0), kRows);
   const int hi = min(max((rel + z) >> 6, -1), kRows - 1);
@@ -257,6 +260,12 @@ __device__ __forceinline__ void row_masks(int2 w, int2 jz, int t_lo, int t_hi, u
   const unsigned core = zone_rows_v(rel, jz.y >> 16);
   fm = (rows & ~(near | edge)) | (((near | edge) & rows) << 16);
   nc = (near & rows) | (core << 16);
+  const bool far_field = w.x <= t_lo && w.y >= t_hi && near == 0u &&
+                         (rel < -kFFDist || rel > kWavePoints - 1 + kFFDist);
+  if (far_field) {
+    fm = 0u;
+    nc = 0u;
+  }
 }
 
 __device__ __forceinline__ void line32(const Rec32& l, unsigned far_masked, unsigned near_core,
@@ -308,6 +317,29 @@ __device__ __forceinline__ void line32(const Rec32& l, unsigned far_masked, unsi
   }
 }
 
+// A far-field record at this lane's node, added with compensation to the
+// node's sum in LDS (kept out of registers: the row sums use them all).
+__device__ __forceinline__ void far_field32(const Rec32& l, int t_lo, int lane, float lnq2, float lnq6,
+                                            const QuadConsts* __restrict__ Q, float* __restrict__ lfs,
+                                            float* __restrict__ lfc) {
+  const float ffoff = Q->ff_off[lane];
+  Far32 f;
+  f.c1 = l.c1;
+  f.c2 = l.c1 * lnq2;
+  f.c3 = l.c1 * lnq6;
+  f.step = 0.0f;
+  f.A = l.A;
+  f.B = l.B;
+  f.D = l.D;
+  f.E = l.E;
+  const float d = (float)(l.J - t_lo) + l.phi - ffoff;
+  const float v = far_value(x_of_d32(d, f), f);
+  float sum = lfs[lane], c = lfc[lane];
+  kahan_add(sum, c, v);
+  lfs[lane] = sum;
+  lfc[lane] = c;
+}
+
 // Compensated (Kahan) addition of the partial sums into the row sums: the
 // running sums s stay in registers, their compensations c in LDS.
 __device__ __forceinline__ void flush32(float (&s)[kRows], RowVec& p, float* __restrict__ lc,
@@ -322,14 +354,35 @@ __device__ __forceinline__ void flush32(float (&s)[kRows], RowVec& p, float* __r
   }
 }
 
+// The far field at point k (0..255) of a quarter from its 16 node values
+// (barycentric formula for Chebyshev points of the first kind; no point of
+// the quarter coincides with a node: the closest is 2.2e-5 away in t).
+__device__ __forceinline__ float far_field_at(const float* __restrict__ nodes, int k,
+                                              const QuadConsts* __restrict__ Q) {
+  const float t = ((float)k - 127.5f) * (1.0f / 127.5f);
+  float num = 0.0f, den = 0.0f;
+#pragma unroll
+  for (int n = 0; n < kFFNodes; ++n) {
+    const float r = Q->ff_w[n] * __builtin_amdgcn_rcpf(t - Q->ff_s[n]);
+    num = fmaf(r, nodes[n], num);
+    den += r;
+  }
+  return num / den;
+}
+
 // A whole record with one scalar-memory wait.  Left to itself the compiler
 // loads each field where it is first used, behind the branches of the line
 // routine, and waits for scalar memory three times per line; the empty asm
 // that takes all twelve words in scalar registers puts the loads and their
 // single wait here.
 __device__ __forceinline__ Rec32 load_rec32(const Rec32* __restrict__ p) {
-  const int4* q = reinterpret_cast<const int4*>(p);
-  const int4 a = q[0], b = q[1], c = q[2];
+  // read through the constant address space: the records are not written
+  // while the kernel runs, and a uniform constant load is always a scalar
+  // load (a global one only when the compiler proves nothing clobbers it)
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  typedef const __attribute__((address_space(4))) v4i cv4i;
+  const cv4i* q = (const cv4i*)p;
+  const v4i a = q[0], b = q[1], c = q[2];
   asm volatile("" ::"s"(a.x), "s"(a.y), "s"(a.z), "s"(a.w), "s"(b.x), "s"(b.y), "s"(b.z), "s"(b.w),
                "s"(c.x), "s"(c.y), "s"(c.z), "s"(c.w));
   Rec32 r;
@@ -358,7 +411,9 @@ constexpr int kFlushLines = 64;
 __global__ __launch_bounds__(256, 6) void k_voigt32(Params P, Batch B,
                                                     const QuadConsts* __restrict__ Q,
                                                     int tiles_per_point, int total) {
-  __shared__ float lds_c[kWavesPerWG][kWavePoints];   // Kahan compensations
+  // per wave: the Kahan compensations of the row sums, then the far-field
+  // node sums and their compensations (one base address for all three)
+  __shared__ float lds_c[kWavesPerWG][kWavePoints + 2 * kWave];
   __shared__ float4 lds_ser[kSerTerms * kSerIntervals]; // small-damping series table
   const int logical = tile_order(blockIdx.x, total);
   if (logical >= total) return;
@@ -378,6 +433,11 @@ __global__ __launch_bounds__(256, 6) void k_voigt32(Params P, Batch B,
   if (t_lo >= N) return;
   const int t_hi = min(t_lo + kWavePoints - 1, N - 1);
   float* lc = lds_c[wid];
+  float* lfs = lc + kWavePoints;
+  float* lfc = lfs + kWave;
+  lfs[lane] = 0.0f;
+  lfc[lane] = 0.0f;
+  bool any_ff = false;
   float s[kRows];
   RowVec p;
 #pragma unroll
@@ -419,6 +479,16 @@ __global__ __launch_bounds__(256, 6) void k_voigt32(Params P, Batch B,
     if (!m) continue;
     unsigned fm, nc;
     row_masks(cur, cz, t_lo, t_hi, fm, nc);
+    // far-field records in a loop of their own (a branch between the two
+    // kinds inside one loop costs the row sums' registers spills)
+    unsigned long long mf = m & __ballot(fm == 0u);
+    m &= ~mf;
+    if (mf) any_ff = true;
+    while (mf) {
+      const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(mf));
+      mf &= mf - 1;
+      far_field32(load_rec32(rec + base + k), t_lo, lane, lnq2, lnq6, Q, lfs, lfc);
+    }
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(m));
       m &= m - 1;
@@ -431,11 +501,14 @@ __global__ __launch_bounds__(256, 6) void k_voigt32(Params P, Batch B,
     }
   }
   flush32(s, p, lc, lane);
+  if (any_ff) lfs[lane] -= lfc[lane];   // node values, read by every lane below
   float* kap = reinterpret_cast<float*>(B.kappa) + pt * B.kappa_stride;
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) {
     const int j = t_lo + rr * 64 + lane;
-    if (j <= t_hi) kap[j] = s[rr] - lc[rr * 64 + lane];
+    const float v = s[rr] - lc[rr * 64 + lane];
+    const float w = any_ff ? far_field_at(lfs + kFFNodes * (rr >> 2), 64 * (rr & 3) + lane, Q) : 0.0f;
+    if (j <= t_hi) kap[j] = v + w;
   }
 }
 

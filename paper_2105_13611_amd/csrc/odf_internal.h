@@ -58,6 +58,23 @@ constexpr float kSerYMax = 0.4f;
 constexpr int kSerTerms = 4;
 constexpr int kSerIntervals = 128;
 
+// FP32 far field of a tile: a line whose window covers the wave's whole tile,
+// whose |x| < 15 zone misses it and whose centre lies more than kFFDist
+// points outside it adds a smooth function of the grid index to the tile.
+// Such lines are evaluated only at kFFNodes Chebyshev points (first kind) in
+// each quarter of the tile, one per lane, and their sum is interpolated to
+// the tile's points at the end.  The poles of a line's two-node fraction lie
+// within sqrt(a^2 + 1/2) Doppler widths of its centre (in the complex plane;
+// off the real axis for large a), and the centre is more than kFFDist points
+// and more than 15 Doppler widths from the tile, so every pole is at least
+// 0.9 kFFDist = 58 points outside it: at least 186 points from the middle
+// of the nearest 256-point quarter (half-length 128).  The interpolation
+// error is then below rho^-16, rho = s + sqrt(s^2 - 1), s = 186/128: 4e-7 of
+// that line's part.
+constexpr int kFFNodes = 16;
+constexpr int kFFQuarter = 256;
+constexpr int kFFDist = 64;
+
 // Half-width in fine points of the zone where |x| < R may occur, for a line
 // with c1 = ln q / b: |x| >= R implies |d| >= R / (1.02 c1) (|d ln q| <= 0.031).
 __host__ __device__ inline int32_t zone_half(double R, double c1) {
@@ -77,6 +94,10 @@ struct QuadConsts {
   double gh4_wd[2];        // omega_k / pi
   double tr64_ci[2 * kTrap64Half + 1];
   double tr64_ch[2 * kTrap64Half + 1];
+  float ff_s[kFFNodes];    // Chebyshev points cos((2n + 1) pi / 32)
+  float ff_w[kFFNodes];    // their barycentric weights (-1)^n sin((2n + 1) pi / 32)
+  float ff_off[64];        // node of lane l, in points after the tile's first point:
+                           // Chebyshev point l % 16 of quarter l / 16
   // T_{2k+1} on interval i: c0 + c1 f + c2 f^2 + c3 f^3, f = s kSerIntervals - i
   alignas(16) float ser[kSerTerms][kSerIntervals][4];
 };

@@ -165,6 +165,16 @@ QuadConsts make_quad_consts() {
     Q.tr64_ci[k + kTrap64Half] = std::fabs(ti) <= tm ? (double)(h / pi * std::exp(-ti * ti)) : 0.0;
     Q.tr64_ch[k + kTrap64Half] = std::fabs(th) <= tm ? (double)(h / pi * std::exp(-th * th)) : 0.0;
   }
+  for (int n = 0; n < kFFNodes; ++n) {
+    const long double th = (2 * n + 1) * pi / (2 * kFFNodes);
+    Q.ff_s[n] = (float)std::cos(th);
+    Q.ff_w[n] = (float)((n % 2 ? -1.0L : 1.0L) * std::sin(th));
+  }
+  for (int l = 0; l < 64; ++l) {
+    const long double th = (2 * (l % kFFNodes) + 1) * pi / (2 * kFFNodes);
+    const long double half = 0.5L * (kFFQuarter - 1);
+    Q.ff_off[l] = (float)(kFFQuarter * (l / kFFNodes) + half + half * std::cos(th));
+  }
   series_table(Q);
   return Q;
 }
