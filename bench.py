@@ -162,6 +162,23 @@ def traffic_per_launch(precision, samples_per_launch=None):
     return d["hbm_bytes_per_launch"]
 
 
+def executed_flop_per_sample(precision):
+    """FP32 (mixed) or FP64 operations the Voigt kernel executed per Voigt
+    sample, from the committed VALU-counter summary of the full-table run, or
+    None when there is none or the kernel has changed since."""
+    path = os.path.join(ROOT, "profiles", f"voigt{32 if precision == 'mixed' else 64}_full_table_valu_flops.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    i = txt.find("```json")
+    if i < 0:
+        return None
+    d = json.loads(txt[i + 7: txt.index("```", i + 7)])
+    if d.get("source_sha256") != kernel_sources_sha256():
+        return None
+    return d["executed_flop_per_sample"]
+
+
 def roofline(res, flop_per_sample, precision):
     st = res["stage_ms"]["voigt"]
     ms, busy, launches = st["ms"], st["busy_ms"], st["launches"]
@@ -178,6 +195,15 @@ def roofline(res, flop_per_sample, precision):
                kernel="voigt scatter-sum", avg_launch_ms=ms / launches,
                busy_ms_per_launch=busy / launches, launches=launches,
                samples_per_launch=samples / launches, flop_per_sample=flop_per_sample)
+    if precision == "mixed":
+        out["note"] = ("achieved counts every Voigt sample of the method (each (line, fine point) pair in "
+                       "the windows) at the far-wing cost; lines whose window covers a 1024-point tile from "
+                       "more than 64 points away are evaluated at 64 nodes of the tile and interpolated, so "
+                       "the kernel evaluates fewer samples: executed is what its VALU did (counters)")
+    e = executed_flop_per_sample(precision)
+    if e is not None:
+        xa = samples * e / (busy / 1e3) / 1e12
+        out["executed"] = dict(flop_per_sample=e, achieved=xa, frac=xa / PEAK_VALU_TFLOPS)
     ka = res.get("kernel_alone")
     if ka and ka["ms"] > 0:
         a = ka["samples"] * flop_per_sample / (ka["ms"] / 1e3) / 1e12

@@ -176,6 +176,9 @@ def flops(args):
               f"- executed {suffix} FLOP per sample (FMA = 2, all 64 lanes counted): {per_sample:.2f}",
               f"- at the profiled run's sample rate ({j.get('voigt_samples_per_s', 0):.4e}/s, which the "
               f"profiler slows): {rate:.2f} TFLOP/s" if rate else ""]
+    summary = dict(kernel=args.kernel, source_sha256=kernel_sources_sha256(),
+                   executed_flop_per_sample=per_sample, voigt_samples=samples, launches=len(launches))
+    lines += ["", "```json", json.dumps(summary, indent=1), "```"]
     open(args.out, "w").write("\n".join(lines) + "\n")
 
 

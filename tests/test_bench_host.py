@@ -49,6 +49,21 @@ def test_traffic_summary_lookup():
             assert t is None
 
 
+def test_executed_flop_summary_lookup():
+    for prec in ("mixed", "fp64"):
+        e = bench.executed_flop_per_sample(prec)
+        path = os.path.join(ROOT, "profiles", f"voigt{32 if prec == 'mixed' else 64}_full_table_valu_flops.md")
+        txt = open(path).read()
+        if "```json" not in txt:
+            assert e is None
+            continue
+        d = json.loads(txt[txt.index("```json") + 7: txt.index("```", txt.index("```json") + 7)])
+        if d["source_sha256"] == bench.kernel_sources_sha256():
+            assert e == d["executed_flop_per_sample"] and e > 0
+        else:
+            assert e is None
+
+
 def test_stratified_points_hold_the_corners():
     pts = W.dfsynthe_tp_grid((2.0,))
     idx = bench.stratified_points(pts, 16)
