@@ -1,0 +1,61 @@
+"""Far field of the mixed Voigt sums.
+
+A (line, tile) pair whose window covers the whole 1024-point tile, whose
+|x| < 15 zone misses it and whose centre lies more than 64 points outside it
+is evaluated at 64 nodes of the tile and interpolated.  Five strong, strongly
+damped lines (two centred outside the grid) with windows over the whole grid
+of config 1 put most (line, tile) pairs of every point in that regime, so the
+fine-grid opacity checks the interpolation against the oracle, which adds
+every sample.  Tolerances as in the other fine-grid tests: 2e-4 (mixed) and
+1e-10 (FP64, which adds every sample too) relative to max(kappa, floor).
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_13611_amd import workload as W
+from tests.gpu_helpers import ambiguous_points, floor_values
+
+pytestmark = pytest.mark.gpu
+
+TOL_FINE = {"fp64": 1e-10, "mixed": 2e-4}
+
+
+@pytest.fixture(scope="module")
+def wide():
+    w = W.config(1)
+    lf = w.layout.lambda_first_nm
+    lam = np.array([lf * 0.995, lf * 1.008, lf * 1.017, lf * 1.026, lf * 1.04])
+    n = lam.size
+    lines = W.Lines(lambda_nm=lam, log_gf=np.full(n, 3.0), e_low_ev=np.zeros(n),
+                    species=(np.arange(n) % w.species.n_species).astype(np.int32),
+                    stage=np.zeros(n, np.int32), log_g_rad=np.full(n, 10.5),
+                    log_g_stark=np.full(n, -5.0), log_g_vdw=np.full(n, -7.0))
+    pts = W.config(2).points
+    pick = np.array([0, 300, 612, 1424])   # 2000 K to 200 000 K, log P -4 to 8
+    return replace(w, lines=lines, points=pts.take(pick),
+                   options=replace(w.options, window_cap_doppler=2000.0))
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_far_field_fine_grid(wide, prec):
+    from paper_2105_13611_amd import odf
+    w = wide
+    with odf.plan_for(w, precision=prec, workspace_bytes=256 << 20) as plan:
+        for i in range(w.points.n_points):
+            lq = oracle.line_quantities(w.lines, w.species, w.species.abundance, float(w.points.T_K[i]),
+                                        float(w.points.log10_P[i]), float(w.points.vturb_kms[i]),
+                                        w.layout, w.options)
+            N = lq["N"]
+            # the case is only a test of the far field if windows span many tiles
+            span = lq["jhi"][lq["surv"]] - lq["jlo"][lq["surv"]] + 1
+            assert lq["surv"].sum() >= 3 and span.max() >= 8 * 1024
+            kap = plan.stage_fine(w.species.abundance, w.points, i).double().cpu().numpy()
+            ref = oracle.fine_opacity(lq, w.layout, 0, N)
+            fl = floor_values(w.layout, w.options, 0, N)
+            err = np.abs(kap - ref) / np.maximum(ref, fl)
+            err[ambiguous_points(lq, N)] = 0.0
+            print(f"{prec} point {i}: fine-grid max err {err.max():.3e}")
+            assert err.max() <= TOL_FINE[prec]
