@@ -10,7 +10,9 @@
 // windows with one ballot, broadcasts each intersecting record with readlane
 // and evaluates only the rows the window covers.  No atomics: each point is
 // summed by one lane in the survivors' wavelength order, so results are
-// bit-reproducible.
+// bit-reproducible.  In FP32, a line whose part is smooth over the whole
+// tile (window over the tile, centre far outside it) is evaluated only at
+// 64 nodes of the tile, whose sums are interpolated at the end.
 //
 // Re w is evaluated in real arithmetic only, so that its relative accuracy
 // holds where Re w << |w| (far wings of weakly damped lines):
