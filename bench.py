@@ -15,7 +15,13 @@ uses the union of the launch intervals (the two internal streams overlap
 launches), and the HBM traffic comes from the committed counter summary
 while the kernel sources still match it.
 The CPU baseline times the FP64 oracle on a bounded stratified sample of the
-same workload and scales it to points/s.
+same workload and scales it to points/s.  It runs first, before anything
+touches the GPU, and its oracle ODF steps are kept: the line's "parity" block
+compares both GPU paths with them at the sampled (point, bin) pairs.
+
+The headline mixed leg runs the given --steps/--warmup; the plain FP64 leg,
+about six times slower per table, runs its own bounded count (--fp64-steps,
+--fp64-warmup; 2 and 1 by default), stated in the line.
 
 --mode pretab times the pre-tabulated high-resolution opacity of a
 wavelength interval (one value per fine point) over the same T-P table and
@@ -57,11 +63,15 @@ FLOP_PER_SAMPLE_F32 = 11.8
 # X 1, numerator and denominator Horner chains 14, reciprocal with one Newton
 # step 5, product and accumulate 3, edge mask 3
 FLOP_PER_SAMPLE_F64 = 28
-# VALU peak without packed FP32 (disabled in this build): 256 CU x 4 SIMD x
-# 16 lanes x 2 FLOP per FMA x 2.4 GHz
+# VALU rate without packed FP32 (disabled in this build): 256 CU x 4 SIMD x
+# 16 lanes x 2 FLOP per FMA x 2.4 GHz, a ceiling reported beside the
+# published peaks
 PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# published MI355X vector peaks: FP32 (with packed FP32 instructions) and FP64
 PEAK_F32_DATASHEET = 157.3
 PEAK_F64_DATASHEET = 78.6
+# parity tolerances per ODF step (relative): mixed path and plain FP64 path
+TOL = {"mixed": 1e-3, "fp64": 1e-9}
 
 
 def log(*a):
@@ -82,7 +92,12 @@ def stratified_points(points, n, seed=2):
     return np.array(sorted(set(idx[:n])), dtype=np.int64)
 
 
-def run_gpu(w, precision, steps, warmup, workspace_gb, points_idx=None, batch_points=0):
+def run_gpu(w, precision, steps, warmup, workspace_gb, points_idx=None, batch_points=0, sample=None):
+    """One leg: plan, `warmup` untimed steps, `steps` timed steps over the
+    table (or its stratified subset).  sample = (point indices into
+    w.points, bins): the output at those pairs is returned for the parity
+    block (points outside this leg's subset are left out)."""
+    import numpy as np
     import torch
     from paper_2105_13611_amd import odf
     pts = w.points if points_idx is None else w.points.take(points_idx)
@@ -104,9 +119,17 @@ def run_gpu(w, precision, steps, warmup, workspace_gb, points_idx=None, batch_po
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     times = plan.stage_times(reset=True)
-    res = dict(precision=precision, seconds=dt, steps=steps, n_points=pts.n_points,
+    res = dict(precision=precision, seconds=dt, steps=steps, warmup=warmup, n_points=pts.n_points,
                plan_seconds=t_plan, stats=stats, stage_ms=times,
                batch_points=None, checksum=float(out.double().sum().item()))
+    if sample is not None:
+        where = (np.arange(w.points.n_points) if points_idx is None else np.asarray(points_idx))
+        row = {int(g): k for k, g in enumerate(where)}
+        got = {}
+        for i in sample[0]:
+            if int(i) in row:
+                got[int(i)] = out[row[int(i)]][list(sample[1])].double().cpu().numpy()
+        res["sample_out"] = got
     res["kernel_alone"] = kernel_alone(plan, w)
     plan.destroy()
     del out
@@ -180,34 +203,46 @@ def executed_flop_per_sample(precision):
 
 
 def roofline(res, flop_per_sample, precision):
+    """Roofline of the Voigt kernel of one leg.  achieved = the method's
+    FLOP per launch (Voigt samples per launch x nominal FLOP per sample) over
+    the kernel's average launch duration (HIP events on the launch's stream,
+    the figure rocprofv3's kernel trace reports); peak = the published vector
+    peak of the path's type (FP32 157.3, FP64 78.6 TFLOP/s).  The two summing
+    streams overlap launches, so a launch's duration includes time it shares
+    the GPU; achieved_busy uses the union of the launch intervals instead.
+    The mixed path also carries the non-packed FP32 rate (packed FP32 is
+    disabled in this build) as a ceiling of its own."""
     st = res["stage_ms"]["voigt"]
     ms, busy, launches = st["ms"], st["busy_ms"], st["launches"]
     samples = res["stats"]["voigt_samples"] * res["steps"]
-    if launches == 0 or busy <= 0:
+    if launches == 0 or busy <= 0 or ms <= 0:
         return None
-    # launches of the two internal streams overlap: a launch's own duration
-    # counts time it shares the GPU with the other stream, so the rate is
-    # taken over the union of the kernel's launch intervals
+    peak = PEAK_F32_DATASHEET if precision == "mixed" else PEAK_F64_DATASHEET
     flop_per_launch = samples * flop_per_sample / launches
-    achieved = flop_per_launch / (busy / 1e3 / launches) / 1e12
-    out = dict(bound="alu", achieved=achieved, peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
-               frac=achieved / PEAK_VALU_TFLOPS, traffic=traffic_per_launch(precision, samples / launches),
-               kernel="voigt scatter-sum", avg_launch_ms=ms / launches,
-               busy_ms_per_launch=busy / launches, launches=launches,
-               samples_per_launch=samples / launches, flop_per_sample=flop_per_sample)
+    achieved = flop_per_launch / (ms / 1e3 / launches) / 1e12
+    achieved_busy = flop_per_launch / (busy / 1e3 / launches) / 1e12
+    out = dict(bound="alu", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+               traffic=traffic_per_launch(precision, samples / launches),
+               kernel="k_voigt32" if precision == "mixed" else "k_voigt64",
+               avg_launch_ms=ms / launches, busy_ms_per_launch=busy / launches, launches=launches,
+               samples_per_launch=samples / launches, flop_per_sample=flop_per_sample,
+               achieved_busy=achieved_busy, frac_busy=achieved_busy / peak)
     if precision == "mixed":
+        out["ceiling_nonpacked"] = dict(peak=PEAK_VALU_TFLOPS, frac=achieved / PEAK_VALU_TFLOPS,
+                                        note="256 CU x 4 SIMD x 16 lanes x 2 FLOP per FMA x 2.4 GHz: the "
+                                             "FP32 rate without packed FP32 instructions")
         out["note"] = ("achieved counts every Voigt sample of the method (each (line, fine point) pair in "
                        "the windows) at the far-wing cost; lines whose window covers a 1024-point tile from "
                        "more than 64 points away are evaluated at 64 nodes of the tile and interpolated, so "
                        "the kernel evaluates fewer samples: executed is what its VALU did (counters)")
     e = executed_flop_per_sample(precision)
     if e is not None:
-        xa = samples * e / (busy / 1e3) / 1e12
-        out["executed"] = dict(flop_per_sample=e, achieved=xa, frac=xa / PEAK_VALU_TFLOPS)
+        xa = samples * e / (ms / 1e3) / 1e12
+        out["executed"] = dict(flop_per_sample=e, achieved=xa, frac=xa / peak)
     ka = res.get("kernel_alone")
     if ka and ka["ms"] > 0:
         a = ka["samples"] * flop_per_sample / (ka["ms"] / 1e3) / 1e12
-        out["kernel_alone"] = dict(achieved=a, frac=a / PEAK_VALU_TFLOPS,
+        out["kernel_alone"] = dict(achieved=a, frac=a / peak,
                                    avg_launch_ms=ka["ms"] / ka["launches"], launches=ka["launches"],
                                    points=ka["points"], batch_points=ka["batch_points"],
                                    note="same kernel with no other kernel beside it (requests of one batch "
@@ -216,39 +251,74 @@ def roofline(res, flop_per_sample, precision):
     return out
 
 
-def cpu_baseline(w, seconds_budget, workers):
+def cpu_sample(w):
+    """The CPU leg's sample: 16 stratified points of the table and three
+    bins (first, a third and two thirds along the ramp)."""
+    nb = w.layout.n_bins
+    return stratified_points(w.points, 16), [0, nb // 3, (2 * nb) // 3]
+
+
+def cpu_baseline(w, workers):
     """Oracle throughput on a stratified sample of points and bins, scaled to
     points/s over the same table: per point, the line stage is timed in full
     and the Voigt sum on a few bins, extrapolated by the point's total sample
-    count (which the oracle's line stage reports for the whole grid)."""
+    count (which the oracle's line stage reports for the whole grid).  Runs
+    before anything touches the GPU (the pool forks this process).  Returns
+    the baseline and the oracle's ODF steps at the sampled (point, bin)
+    pairs, for the parity block."""
     import multiprocessing as mp
     import numpy as np
-    n_pts = 16
-    idx = stratified_points(w.points, n_pts)
-    e = w.layout.bin_edges
-    nb = len(e) - 1
-    bins = [0, nb // 3, (2 * nb) // 3]
-    tasks = [(w, int(i), bins) for i in idx]
+    global _CPU_W
+    idx, bins = cpu_sample(w)
+    tasks = [(int(i), bins) for i in idx]
+    # the forked workers inherit the workload; tasks carry only indices
+    _CPU_W = w
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(min(workers, len(tasks))) as pool:
-        per = pool.map(_cpu_task, tasks)
+    try:
+        with mp.get_context("fork").Pool(min(workers, len(tasks))) as pool:
+            per = pool.map(_cpu_task, tasks, chunksize=1)
+    finally:
+        _CPU_W = None
     wall = time.perf_counter() - t0
     core_s = [p["t_lines"] + p["t_bins"] * p["samples_total"] / max(p["samples_bins"], 1) for p in per]
     mean_core_s = float(np.mean(core_s))
     value = workers / mean_core_s
-    return dict(value=value, unit="points/s", cores=workers, kind="oracle",
+    base = dict(value=value, unit="points/s", cores=workers, kind="oracle",
                 sample=(f"{len(idx)} stratified (T,P) points of the table x bins {bins} "
                         f"({sum(p['samples_bins'] for p in per)} Voigt samples, wall {wall:.1f} s on "
                         f"{min(workers, len(tasks))} processes); per point the line stage is timed in "
                         f"full and the bin sums are scaled by total/sampled Voigt samples; "
                         f"points/s = cores / mean core-seconds per point ({mean_core_s:.0f} s)"),
                 wall_s=wall, mean_core_s_per_point=mean_core_s)
+    ref = {p["point"]: dict(steps=p["steps"], near_tie=p["near_tie"]) for p in per}
+    return base, ref, bins
+
+
+def _near_tie_bins(lq, edges, bins):
+    """Bins whose fine-grid opacity depends on a decision that floating
+    point takes within rounding of its boundary (a keep test with
+    |core/thr - 1| < 1e-11, or a window edge within 1e-7 of an integer):
+    there either result is valid, so the parity block counts them."""
+    import numpy as np
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tie = np.abs(lq["core"] / lq["thr"] - 1.0) < 1e-11
+    tie |= lq["keep"] & ((np.abs(lq["jlo_r"] - np.round(lq["jlo_r"])) < 1e-7)
+                         | (np.abs(lq["jhi_r"] - np.round(lq["jhi_r"])) < 1e-7))
+    out = []
+    for b in bins:
+        j0, j1 = int(edges[b]), int(edges[b + 1])
+        out.append(bool(np.any(tie & (lq["jlo"] - 1 <= j1 - 1) & (lq["jhi"] + 1 >= j0))))
+    return out
+
+
+_CPU_W = None
 
 
 def _cpu_task(args):
     import numpy as np
     import oracle
-    w, i, bins = args
+    w = _CPU_W
+    i, bins = args
     T, lp, v = float(w.points.T_K[i]), float(w.points.log10_P[i]), float(w.points.vturb_kms[i])
     t0 = time.perf_counter()
     lq = oracle.line_quantities(w.lines, w.species, w.species.abundance, T, lp, v, w.layout, w.options)
@@ -257,6 +327,7 @@ def _cpu_task(args):
     total = int(np.sum(lq["jhi"][s] - lq["jlo"][s] + 1))
     e = w.layout.bin_edges
     nsb = 0
+    steps = []
     t0 = time.perf_counter()
     for b in bins:
         j0, j1 = int(e[b]), int(e[b + 1])
@@ -264,9 +335,36 @@ def _cpu_task(args):
         nsb += int(np.sum(np.minimum(lq["jhi"][m], j1 - 1) - np.maximum(lq["jlo"][m], j0) + 1))
         kl = oracle.fine_opacity(lq, w.layout, j0, j1)
         fl = w.options.cutoff * oracle.physics.kappa_c(oracle.grid_lambda_nm(w.layout, np.arange(j0, j1)), w.options)
-        oracle.odf_reduce_bin(np.maximum(kl, fl), w.layout.step_frac, w.options.mean)
+        steps.append(oracle.odf_reduce_bin(np.maximum(kl, fl), w.layout.step_frac, w.options.mean))
     t_bins = time.perf_counter() - t0
-    return dict(point=i, t_lines=t_lines, t_bins=t_bins, samples_total=total, samples_bins=nsb)
+    return dict(point=i, t_lines=t_lines, t_bins=t_bins, samples_total=total, samples_bins=nsb,
+                steps=np.stack(steps), near_tie=_near_tie_bins(lq, e, bins))
+
+
+def parity_block(ref, bins, legs):
+    """Max relative error per ODF step and max |dlog10 kappa| of each GPU
+    leg against the oracle's steps at the CPU leg's sampled pairs."""
+    import numpy as np
+    out = dict(sample=f"{len(ref)} stratified (T,P) points x bins {list(bins)} of the timed table, "
+                      f"oracle steps from the CPU leg", tolerance=dict(TOL))
+    for prec, got in legs.items():
+        rel, dlog, pairs, ties, worst_tie = 0.0, 0.0, 0, 0, 0.0
+        for i, r in ref.items():
+            if i not in got:
+                continue
+            for k in range(len(bins)):
+                g, o = got[i][k], r["steps"][k]
+                e = float(np.max(np.abs(g / o - 1.0)))
+                pairs += 1
+                if r["near_tie"][k]:
+                    ties += 1
+                    worst_tie = max(worst_tie, e)
+                rel = max(rel, e)
+                dlog = max(dlog, float(np.max(np.abs(np.log10(g) - np.log10(o)))))
+        out[prec] = dict(max_rel_err=rel, max_abs_dlog10_kappa=dlog, pairs=pairs,
+                         within_tolerance=bool(pairs > 0 and rel <= TOL[prec]),
+                         bins_with_near_tie_decisions=ties, max_rel_err_in_those=worst_tie)
+    return out
 
 
 def run_serving(n_requests, rate_hz, workspace_gb, max_points, serve_config=4):
@@ -621,6 +719,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--fp64-steps", type=int, default=2,
+                    help="timed steps of the plain FP64 leg (about 25 s each on the full table)")
+    ap.add_argument("--fp64-warmup", type=int, default=1, help="untimed steps of the plain FP64 leg")
     ap.add_argument("--points", type=int, default=0, help="stratified subset (0 = whole table)")
     ap.add_argument("--workspace-gb", type=float, default=80.0)
     ap.add_argument("--batch-points", type=int, default=0, help="points per device batch (0 = automatic)")
@@ -636,38 +737,64 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the ODF table shards over points with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "table":
+        run_table(args)
+        return
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.copy_calibration_mb:
-        n = args.copy_calibration_mb << 18   # float32 elements
-        a = torch.ones(n, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            torch.mul(a, 1.0, out=b)   # an elementwise kernel (a same-type copy_ may use DMA)
-        torch.cuda.synchronize()
-        log(f"[bench] copy calibration: 3 copies of {args.copy_calibration_mb} MiB")
-        del a, b
+    copy_calibration(args)
     if args.mode == "pretab":
         print(json.dumps(run_pretab(args)), flush=True)
         return
     if args.mode == "subbins":
         print(json.dumps(run_subbins(args)), flush=True)
         return
-    if args.mode == "serve":
-        print(json.dumps(run_serving(args.serve_requests, args.serve_rate, args.workspace_gb,
-                                     args.serve_max_points, args.serve_config)), flush=True)
+    print(json.dumps(run_serving(args.serve_requests, args.serve_rate, args.workspace_gb,
+                                 args.serve_max_points, args.serve_config)), flush=True)
+
+
+def copy_calibration(args):
+    """Optionally copy a buffer of known size three times (the reference
+    for rocprofv3's HBM byte counters)."""
+    import torch
+    if not args.copy_calibration_mb:
         return
+    n = args.copy_calibration_mb << 18   # float32 elements
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)   # an elementwise kernel (a same-type copy_ may use DMA)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: 3 copies of {args.copy_calibration_mb} MiB")
+    del a, b
+
+
+def run_table(args):
+    """The table benchmark: the CPU leg first (before anything touches the
+    GPU), then the mixed leg at the given steps, then the plain FP64 leg at
+    its bounded steps; one JSON line."""
     from paper_2105_13611_amd import workload as W
     t0 = time.perf_counter()
     w = W.config(args.config)
     log(f"[bench] workload generated in {time.perf_counter() - t0:.1f} s: {w.lines.n_lines} lines, "
         f"{w.points.n_points} points, {w.layout.n_bins} bins")
     idx = None if args.points == 0 else stratified_points(w.points, args.points)
+    cpu, ref, sbins = None, None, None
+    if not args.no_cpu:
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        log(f"[bench] CPU baseline: oracle on {workers} processes")
+        cpu, ref, sbins = cpu_baseline(w, workers)
+        log(f"[bench] CPU baseline: {cpu['value']:.4f} points/s, wall {cpu['wall_s']:.1f} s")
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    copy_calibration(args)
+    sample = None if ref is None else (sorted(ref), sbins)
     precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     res = {}
     for p in precs:
-        res[p] = run_gpu(w, p, args.steps, args.warmup if p == precs[0] else min(args.warmup, 1),
-                         args.workspace_gb, idx, args.batch_points)
+        steps, warmup = ((args.steps, args.warmup) if p == precs[0] or p == "mixed"
+                         else (args.fp64_steps, args.fp64_warmup))
+        res[p] = run_gpu(w, p, steps, warmup, args.workspace_gb, idx, args.batch_points, sample)
         r = res[p]
         log(f"[bench] {p}: {r['n_points'] * r['steps'] / r['seconds']:.2f} points/s, "
             f"stage ms {r['stage_ms']}, plan {r['plan_seconds']:.1f} s")
@@ -676,11 +803,9 @@ def main():
     value = n_pts * head["steps"] / head["seconds"]
     line_evals = head["stats"]["line_evals"] * head["steps"] / head["seconds"]
     rl = roofline(head, FLOP_PER_SAMPLE_F32 if precs[0] == "mixed" else FLOP_PER_SAMPLE_F64, precs[0])
-    if rl:
-        rl["frac_of_datasheet_fp32"] = rl["achieved"] / (PEAK_F32_DATASHEET if precs[0] == "mixed" else PEAK_F64_DATASHEET)
     out = {
-        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": head["seconds"] / head["steps"] * 1e3,
+        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": head["steps"],
+        "warmup": head["warmup"], "ms_per_step": head["seconds"] / head["steps"] * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if precs[0] == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config]
@@ -696,17 +821,19 @@ def main():
     for p in precs:
         r = res[p]
         out[f"{p}_path"] = dict(points_per_s=r["n_points"] * r["steps"] / r["seconds"],
-                                seconds_per_step=r["seconds"] / r["steps"],
+                                line_evals_per_s=r["stats"]["line_evals"] * r["steps"] / r["seconds"],
+                                seconds_per_step=r["seconds"] / r["steps"], steps=r["steps"],
+                                warmup=r["warmup"],
                                 stage_ms={k: v["ms"] for k, v in r["stage_ms"].items()},
                                 stage_busy_ms={k: v["busy_ms"] for k, v in r["stage_ms"].items()},
                                 plan_seconds=r["plan_seconds"], checksum=r["checksum"])
     if "fp64" in res and "mixed" in res:
         out["mixed_over_fp64_speedup"] = out["mixed_path"]["points_per_s"] / out["fp64_path"]["points_per_s"]
         out["roofline_fp64"] = roofline(res["fp64"], FLOP_PER_SAMPLE_F64, "fp64")
-    if not args.no_cpu:
-        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
-        log(f"[bench] CPU baseline: oracle on {workers} processes")
-        out["cpu_baseline"] = cpu_baseline(w, 20.0, workers)
+    if ref is not None:
+        out["parity"] = parity_block(ref, sbins, {p: res[p].get("sample_out", {}) for p in precs})
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

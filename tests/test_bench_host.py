@@ -21,20 +21,56 @@ def _result():
                 kernel_alone=dict(ms=50.0, busy_ms=50.0, launches=2, samples=2.0e11, points=64, batch_points=16))
 
 
-def test_roofline_uses_the_union_of_launch_intervals():
+def test_roofline_uses_the_average_launch_duration():
     r = bench.roofline(_result(), 10.0, "mixed")
-    # 2 steps x 3e12 samples x 10 FLOP over 0.3 s of busy time
-    assert abs(r["achieved"] - 6.0e13 / 0.3 / 1e12) < 1e-9
-    assert abs(r["frac"] - r["achieved"] / bench.PEAK_VALU_TFLOPS) < 1e-12
+    # 2 steps x 3e12 samples x 10 FLOP over 4 launches of 100 ms each
+    assert abs(r["achieved"] - 6.0e13 / 0.4 / 1e12) < 1e-9
+    assert r["peak"] == 157.3 and abs(r["frac"] - r["achieved"] / 157.3) < 1e-12
+    # the union of the launch intervals is reported beside it
+    assert abs(r["achieved_busy"] - 6.0e13 / 0.3 / 1e12) < 1e-9
     assert r["avg_launch_ms"] == 100.0 and r["busy_ms_per_launch"] == 75.0
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s"
+    c = r["ceiling_nonpacked"]
+    assert abs(c["peak"] - 78.6432) < 1e-9 and abs(c["frac"] - r["achieved"] / c["peak"]) < 1e-12
     ka = r["kernel_alone"]
     assert abs(ka["achieved"] - 2.0e11 * 10.0 / 0.05 / 1e12) < 1e-9
     assert ka["avg_launch_ms"] == 25.0
+    r64 = bench.roofline(_result(), 28.0, "fp64")
+    assert r64["peak"] == 78.6 and "ceiling_nonpacked" not in r64
 
 
-def test_peak_is_the_non_packed_valu_rate():
+def test_nonpacked_ceiling_is_the_valu_rate():
     assert abs(bench.PEAK_VALU_TFLOPS - 78.6432) < 1e-9
+
+
+def test_parity_block():
+    ref = {3: dict(steps=np.array([[1.0, 2.0], [4.0, 8.0]]), near_tie=[False, True]),
+           7: dict(steps=np.array([[1.0, 1.0], [2.0, 2.0]]), near_tie=[False, False])}
+    got = {"mixed": {3: np.array([[1.0005, 2.0], [4.0, 8.0]]), 7: np.array([[1.0, 1.0], [2.0, 2.0]])},
+           "fp64": {3: np.array([[1.0, 2.0], [4.0, 8.0 * (1 + 3e-9)]])}}
+    pb = bench.parity_block(ref, [10, 20], got)
+    m, f = pb["mixed"], pb["fp64"]
+    assert m["pairs"] == 4 and abs(m["max_rel_err"] - 5e-4) < 1e-12 and m["within_tolerance"]
+    assert abs(m["max_abs_dlog10_kappa"] - np.log10(1.0005)) < 1e-12
+    assert m["bins_with_near_tie_decisions"] == 1 and m["max_rel_err_in_those"] == 0.0
+    # point 7 was not in the FP64 leg's points: only point 3 counts
+    assert f["pairs"] == 2 and abs(f["max_rel_err"] - 3e-9) < 1e-15 and not f["within_tolerance"]
+    assert abs(f["max_rel_err_in_those"] - 3e-9) < 1e-15
+
+
+def test_cpu_leg_keeps_the_oracle_steps():
+    """The CPU leg on the small single-point workload: its kept steps are
+    the oracle's ODF of those bins."""
+    import oracle
+    w = W.config(1, n_lines=300)
+    base, ref, bins = bench.cpu_baseline(w, 2)
+    assert base["kind"] == "oracle" and base["cores"] == 2 and base["value"] > 0
+    assert sorted(ref) == [0] and bins == [0, 6, 13]
+    steps, _, _ = oracle.odf_point(w.lines, w.species, w.species.abundance, float(w.points.T_K[0]),
+                                   float(w.points.log10_P[0]), float(w.points.vturb_kms[0]), w.layout,
+                                   w.options, bins)
+    np.testing.assert_array_equal(ref[0]["steps"], steps)
+    assert len(ref[0]["near_tie"]) == 3
 
 
 def test_traffic_summary_lookup():
