@@ -282,6 +282,37 @@ odf_status odf_stage_reduce(odf_plan_t *plan, const void *kappa_dev, void *out_d
 odf_status odf_stage_times(odf_plan_t *plan, double *ms, double *busy_ms, int64_t *launches,
                            int32_t reset);
 
+/* ---- allocation-free entry point -------------------------------------- */
+
+/* For callers that cannot allocate device memory or wait (code under HIP
+ * graph capture, serving loops that forbid allocation): the ODF reduction
+ * of odf_stage_reduce (floor, per-bin sort, sub-bin means) over n_points
+ * fine grids, enqueued on `stream` (NULL: options.stream) and not waited
+ * for.  It calls no allocator: bins too large for LDS sort in a static
+ * device array of the library, 32 MiB per GPU (held until the process
+ * ends), instead of the plan's workspace.
+ *   kappa_dev  device [n_points][N], float (MIXED plan) or double (FP64),
+ *              read only; caller-owned, valid until the work completes
+ *   out_dev    device [n_points][n_bins][n_steps] of the same type, written
+ *              in full once the stream reaches this work
+ * Must be called with the plan's device current.  Every call on one GPU,
+ * from any plan, shares that GPU's array and keeps what the last call left
+ * there: two calls whose work overlaps on the device (on different streams)
+ * race, and the caller must order them.  odf_compute, the request loop and
+ * odf_stage_reduce do not use the array.  Nothing in it needs clearing:
+ * each call writes every scratch key before it reads it.
+ * Errors: ODF_E_INVALID (NULL plan or buffer, n_points outside [0, 65535],
+ * a plan with output = fine, another device current), ODF_E_NOMEM when the
+ * oversize bins of n_points grids need more scratch than the array holds
+ * (odf_noalloc_scratch_need), ODF_E_DEVICE on a launch error. */
+odf_status odf_reduce_noalloc(odf_plan_t *plan, const void *kappa_dev, int32_t n_points,
+                              void *out_dev, void *stream);
+
+/* Bytes of static scratch that odf_reduce_noalloc needs for n_points grids
+ * of this plan (0 when every bin fits LDS), or -1 for a NULL plan or
+ * negative count. */
+int64_t odf_noalloc_scratch_need(const odf_plan_t *plan, int32_t n_points);
+
 /* Test hook for failure handling: the next batch of `ticket` that the
  * request loop launches reports a launch error instead of running, so the
  * ticket ends FAILED while every other ticket completes normally. */

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libodf.so")
-SOURCES = ["k_lines.hip", "k_voigt.hip", "k_odf.hip", "quadrature.cpp", "plan.cpp", "loop.cpp"]
+SOURCES = ["k_lines.hip", "k_voigt.hip", "k_odf.hip", "noalloc.hip", "quadrature.cpp", "plan.cpp",
+           "loop.cpp"]
 ARCH = "gfx950"
 
 

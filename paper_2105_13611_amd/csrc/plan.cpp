@@ -407,6 +407,10 @@ odf_status odf_plan(const odf_lines* lines, const odf_species* species, const od
 
   std::unique_ptr<odf_plan_s> p(new odf_plan_s());
   p->opts = *opts;
+  HIP_TRY(hipGetDevice(&p->device));
+  // the allocation-free reduction's static scratch: its address on this
+  // device, resolved here once so that odf_reduce_noalloc needs no set-up
+  if (!noalloc_scratch(p->device)) return ODF_E_DEVICE;
   if (p->opts.loop_streams == 0) p->opts.loop_streams = 2;
   p->n_species = species->n_species;
   p->n_stages = species->n_stages;

@@ -36,6 +36,13 @@ constexpr int kPipeSlots = 4;
 // Newton steps allowed to the ionisation equilibrium of a point.
 constexpr int kNeMaxSteps = 100;
 
+// Size of the static device array that odf_reduce_noalloc sorts oversize
+// bins in (one copy per GPU, held until the process ends).
+constexpr int64_t kNoAllocScratchBytes = 32ll << 20;
+// Device address of that array on device `dev`, resolved once per device
+// (noalloc.hip); nullptr with the error set on failure.
+void* noalloc_scratch(int dev);
+
 // HIP-event timing of the kernels that odf_compute launches (opt-in).
 constexpr int kStages = 6;
 struct StageTimer {
@@ -55,6 +62,7 @@ class RequestLoop;    // (loop.cpp)
 struct odf_plan_s {
   // validated copies
   odf_options opts{};
+  int device = -1;                  // HIP device current when the plan was built
   int32_t n_species = 0, n_stages = 0;
   int64_t n_lines = 0, N = 0;
   int32_t n_bins = 0, n_steps = 0;

@@ -94,6 +94,8 @@ SIGNATURES = {
     "odf_debug_fail_next_batch": (C.c_int, [C.c_void_p, C.c_int64]),
     "odf_debug_set_newton_limit": (C.c_int, [C.c_void_p, C.c_int32]),
     "odf_stage_times": (C.c_int, [C.c_void_p, _D, _D, _I64, C.c_int32]),
+    "odf_reduce_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "odf_noalloc_scratch_need": (C.c_int64, [C.c_void_p, C.c_int32]),
 }
 
 
@@ -362,6 +364,22 @@ class Plan:
         r, keep = _request(abundance, points, 0)
         _check(lib().odf_stage_fine(self.handle, C.byref(r), int(point), C.c_void_p(kap.data_ptr())))
         return kap
+
+    def noalloc_scratch_need(self, n_points):
+        return int(lib().odf_noalloc_scratch_need(self.handle, int(n_points)))
+
+    def reduce_noalloc(self, kappa, out):
+        """ODF tables of kappa [n][N] into out [n][bins][steps] (both device
+        tensors of the plan's type, caller-allocated) through the
+        allocation-free entry point, on the plan's stream; not waited for."""
+        n = int(kappa.shape[0])
+        for t, shape in ((kappa, (n, self.N)), (out, (n, self.n_bins, self.n_steps))):
+            if t.dtype != self.out_dtype or t.device != self.device or not t.is_contiguous() \
+                    or tuple(t.shape) != shape:
+                raise ValueError(f"expected a contiguous {self.out_dtype} tensor {shape} on {self.device}")
+        _check(lib().odf_reduce_noalloc(self.handle, C.c_void_p(kappa.data_ptr()), n,
+                                        C.c_void_p(out.data_ptr()), C.c_void_p(self.stream.cuda_stream)))
+        return out
 
     def stage_reduce(self, kappa):
         kappa = kappa.to(device=self.device, dtype=self.out_dtype).contiguous()
