@@ -252,6 +252,27 @@ odf_status odf_stage_lines(odf_plan_t *plan, const odf_request *req, int32_t poi
                            int64_t *orig_index, int32_t *j_lo, int32_t *j_hi,
                            double *S, double *a, double *b);
 
+/* Survivor records of point `point` of req exactly as this plan's Voigt
+ * kernel reads them, in wavelength order (the order of odf_stage_lines),
+ * for checking the values the kernel trusts.  MIXED plans: 48-byte FP32
+ * records (int32 J = nearest index of the line centre, j_lo, j_hi, packed
+ * zone half-widths; float phi = centre - J, c1 = sigma ln q / b, the
+ * far-wing fraction S H = (A v + B) / (v^2 + E) with v = u^2 + D and
+ * u = sigma x, S, a; sigma = 1, or 1/a in the Lorentz limit a >= 1e4),
+ * and in wz_host [2 n_surv] the (J, packed zone half-widths) pairs read
+ * beside the windows; the zone half-widths are the fine points around J
+ * where |x| < 15 (low 16 bits) and |x| < 6 (high 16 bits) may occur,
+ * -32768 for none.  FP64 plans: 64-byte records (J, j_lo, j_hi, zone
+ * half-widths for |x| < 8 and < 40 or -1, sorted line index, two pads;
+ * double phi, S, a, c1 = ln q / b); wz_host is not used and may be NULL.
+ *   rec_host  host buffer of `capacity` records; *n_surv receives the
+ *             survivor count and *record_bytes the record size.
+ * ODF_E_INVALID when more than `capacity` lines survive (the count is
+ * still returned). */
+odf_status odf_stage_records(odf_plan_t *plan, const odf_request *req, int32_t point,
+                             int64_t *n_surv, int32_t *record_bytes, void *rec_host,
+                             int64_t capacity, int32_t *wz_host);
+
 /* Gas state of point `point` of req (Sec. 2.1; App. A): state host [4]
  * receives n_e, the heavy-particle density N_heavy = P/kT - n_e (with fixed
  * P_e: (P - P_e)/kT), the hydrogen density N_H [cm^-3] and the mass density

@@ -875,6 +875,40 @@ odf_status odf_stage_lines(odf_plan_t* p, const odf_request* r, int32_t point, i
   return ODF_OK;
 }
 
+odf_status odf_stage_records(odf_plan_t* p, const odf_request* r, int32_t point, int64_t* n_surv,
+                             int32_t* record_bytes, void* rec_host, int64_t capacity, int32_t* wz_host) {
+  g_err.clear();
+  if (!p) { set_error("plan is NULL"); return ODF_E_INVALID; }
+  odf_status st = validate_request(p, r, false);
+  if (st != ODF_OK) return st;
+  if (point < 0 || point >= r->n_points) { set_error("point %d out of range", point); return ODF_E_INVALID; }
+  const bool mixed = p->opts.precision == ODF_PREC_MIXED;
+  if (!n_surv || !record_bytes || !rec_host || (mixed && !wz_host)) {
+    set_error("stage_records: NULL output");
+    return ODF_E_INVALID;
+  }
+  std::lock_guard<std::mutex> guard(p->compute_mu);
+  WorkspaceLease lease(p->loop.get());
+  Batch B;
+  if ((st = stage_prefix(p, r, point, &B, mixed ? 0 : 1, nullptr)) != ODF_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(p->opts.stream);
+  int32_t ns = 0;
+  HIP_TRY(hipMemcpyAsync(&ns, B.nsurv, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int64_t rb = mixed ? (int64_t)sizeof(Rec32) : (int64_t)sizeof(Rec64);
+  *n_surv = ns;
+  *record_bytes = (int32_t)rb;
+  if (ns > capacity) {
+    set_error("stage_records: %d survivors, capacity %lld", ns, (long long)capacity);
+    return ODF_E_INVALID;
+  }
+  if (ns > 0) {
+    HIP_TRY(hipMemcpy(rec_host, B.rec, (size_t)ns * rb, hipMemcpyDeviceToHost));
+    if (mixed) HIP_TRY(hipMemcpy(wz_host, B.wz, (size_t)ns * sizeof(int2), hipMemcpyDeviceToHost));
+  }
+  return ODF_OK;
+}
+
 odf_status odf_debug_set_newton_limit(odf_plan_t* p, int32_t max_steps) {
   g_err.clear();
   if (!p) { set_error("plan is NULL"); return ODF_E_INVALID; }

@@ -1,10 +1,23 @@
-"""Parity at the benchmark's full size, on sampled outputs.
+"""Parity at the benchmark's full sizes, on sampled outputs.
 
-The full 1e7-line list, the 3 507 864-point grid and the 1212-bin ramp of the
-benchmark table, computed with the benchmark's workspace (64-point device
-batches), at sampled (T, P, v_turb) points that span the grid's cost range;
-the oracle checks a few bins of each (it needs minutes per point for all).
+* The full 1e7-line list, the 3 507 864-point grid and the 1212-bin ramp of
+  the benchmark table, computed with the benchmark's workspace (one device
+  batch), at sampled (T, P, v_turb) points that span the grid's cost range;
+  the oracle checks three bins of each live.
+* The serving stream over the same list: its first four requests (own
+  compositions, 762-1025 points each) submitted together to the request
+  loop, compared at 4 points x 16 bins per request with the oracle's steps
+  stored by tests/golden/make_sampled_oracle.py.
+* The 1e8-line list over 80 species x 3 stages, both precisions, at 4 points
+  x 8 bins, against the same script's stored oracle steps.
+
+A bin that holds a near-tie decision (keep test or window edge within
+rounding) is compared with the oracle recomputed with the GPU's own
+decisions, after checking they are valid (tests/gpu_helpers.py); no bin is
+skipped.
 """
+import json
+import os
 from dataclasses import replace
 
 import numpy as np
@@ -12,10 +25,12 @@ import pytest
 
 import oracle
 from paper_2105_13611_amd import workload as W
-from tests.gpu_helpers import ambiguous_bins, log10_err, rel_err
+from tests.gpu_helpers import (ambiguous_bins, gpu_decisions, log10_err, oracle_bin_with_gpu_decisions,
+                               rel_err)
 
 pytestmark = pytest.mark.gpu
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 # the benchmark's workspace; the batch then holds all sampled points
 WORKSPACE = 40 << 30
 POINTS = W.Points(np.array([5000.0, 2000.0, 200000.0, 20000.0, 5000.0, 20000.0]),
@@ -24,6 +39,7 @@ POINTS = W.Points(np.array([5000.0, 2000.0, 200000.0, 20000.0, 5000.0, 20000.0])
 # bins checked per point (widths 500, 1280 and 3463 fine points)
 BINS = [0, 400, 1000]
 TOL = {"fp64": 1e-9, "mixed": 1e-3}
+REACH = 1.05   # the fixture script's pre-filter (a superset of the lines that reach a bin)
 
 
 @pytest.fixture(scope="module")
@@ -39,7 +55,7 @@ def reference(full):
         steps, cnt, ex = oracle.odf_point(w.lines, w.species, w.species.abundance, float(POINTS.T_K[i]),
                                           float(POINTS.log10_P[i]), float(POINTS.vturb_kms[i]), w.layout,
                                           w.options, BINS)
-        ref.append((steps, cnt, ambiguous_bins(ex["lq"], w.layout.bin_edges)))
+        ref.append((steps, cnt, ambiguous_bins(ex["lq"], w.layout.bin_edges), ex["lq"]))
     return ref
 
 
@@ -48,24 +64,26 @@ def test_full_size_sampled_parity(full, reference, prec):
     import torch
     from paper_2105_13611_amd import odf
     w = full
+    worst, worst_log, resolved = 0.0, 0.0, 0
     with odf.plan_for(w, precision=prec, workspace_bytes=WORKSPACE) as plan:
         out, st = plan.compute(w.species.abundance, POINTS)
         got = out.double().cpu().numpy()
-    torch.cuda.synchronize()
-    worst, worst_log, skipped = 0.0, 0.0, 0
-    for i, (steps, cnt, amb) in enumerate(reference):
-        for k, b in enumerate(BINS):
-            if b in amb:
-                skipped += 1
-                continue
-            worst = max(worst, float(rel_err(got[i, b], steps[k]).max()))
-            worst_log = max(worst_log, float(log10_err(got[i, b], steps[k]).max()))
-    n_surv = sum(c["survivors"] for _, c, _ in reference)
-    n_samp = sum(c["voigt_samples"] for _, c, _ in reference)
+        torch.cuda.synchronize()
+        for i, (steps, cnt, amb, lq) in enumerate(reference):
+            dec = None
+            for k, b in enumerate(BINS):
+                r = steps[k]
+                if b in amb:
+                    dec = dec or gpu_decisions(plan, w.species.abundance, POINTS, i)
+                    r = oracle_bin_with_gpu_decisions(lq, w.layout, w.options, b, dec)
+                    resolved += 1
+                worst = max(worst, float(rel_err(got[i, b], r).max()))
+                worst_log = max(worst_log, float(log10_err(got[i, b], r).max()))
+    n_surv = sum(c["survivors"] for _, c, _, _ in reference)
+    n_samp = sum(c["voigt_samples"] for _, c, _, _ in reference)
     print(f"full size {prec}: max rel err per step {worst:.3e}, max |dlog10 k| {worst_log:.3e}, "
-          f"skipped {skipped}; survivors {st['survivors']} (oracle {n_surv}), samples {st['voigt_samples']} "
-          f"(oracle {n_samp})")
-    assert skipped <= 2
+          f"near-tie bins {resolved}; survivors {st['survivors']} (oracle {n_surv}), samples "
+          f"{st['voigt_samples']} (oracle {n_samp})")
     assert worst <= TOL[prec]
     assert abs(st["survivors"] - n_surv) <= 6
     assert abs(st["voigt_samples"] - n_samp) <= 6 * 2
@@ -74,41 +92,106 @@ def test_full_size_sampled_parity(full, reference, prec):
     assert np.all(np.diff(got, axis=2) >= -1e-6 * np.abs(got[:, :, 1:]))
 
 
-@pytest.mark.slow
-def test_large_line_list_sampled_parity():
-    """The 1e8-line list over 80 species x 3 stages, at two points and two
-    bins.  The device sums all 1e8 lines; the oracle only needs the lines
-    whose windows can reach the sampled bins: a window spans at most 500
-    Doppler widths, under 3.2 % in wavelength on this grid (2e5 K, 12 amu,
-    8 km/s), so lines within 5 % of a bin's wavelengths are a superset."""
-    import torch
-    from paper_2105_13611_amd import odf
-    w = W.config(5, n_requests=1)
-    assert w.lines.n_lines == 100_000_000 and w.species.n_stages == 3
-    pts = W.Points(np.array([4000.0, 100000.0]), np.array([2.0, -2.0]), np.array([2.0, 8.0]))
-    bins = [150, 800]
-    a = w.requests[0].abundance
-    with odf.plan_for(w, precision="mixed", workspace_bytes=24 << 30) as plan:
-        out, st = plan.compute(a, pts)
-        got = out.double().cpu().numpy()
-    torch.cuda.synchronize()
+def _reach(w, bins):
+    """The fixture script's line subset: lines within REACH of a bin."""
     e = w.layout.bin_edges
     lam = w.lines.lambda_nm
-    worst, skipped = 0.0, 0
+    keep = np.zeros(lam.size, dtype=bool)
     for b in bins:
-        l0 = oracle.grid_lambda_nm(w.layout, e[b])
-        l1 = oracle.grid_lambda_nm(w.layout, e[b + 1] - 1)
-        sub = replace(w, lines=w.lines.take(np.nonzero((lam > l0 / 1.05) & (lam < l1 * 1.05))[0]))
-        for i in range(pts.n_points):
-            steps, _, ex = oracle.odf_point(sub.lines, w.species, a, float(pts.T_K[i]), float(pts.log10_P[i]),
-                                            float(pts.vturb_kms[i]), w.layout, w.options, [b])
-            if b in ambiguous_bins(ex["lq"], e):
-                skipped += 1
-                continue
-            worst = max(worst, float(rel_err(got[i, b], steps[0]).max()))
-    print(f"1e8 lines: max rel err per step {worst:.3e}, skipped {skipped}, survivors {st['survivors']}, "
-          f"samples {st['voigt_samples']}")
-    assert skipped <= 1
-    assert worst <= TOL["mixed"]
-    assert st["line_evals"] == 2 * 100_000_000
+        l0 = float(oracle.grid_lambda_nm(w.layout, e[b]))
+        l1 = float(oracle.grid_lambda_nm(w.layout, e[b + 1] - 1))
+        keep |= (lam > l0 / REACH) & (lam < l1 * REACH)
+    return np.nonzero(keep)[0]
+
+
+def _check_pairs(w, plan, got, ref_steps, near_tie, bins, pts, abundance, tol, sub=None):
+    """Max relative and log10 errors of got[k][bins] against stored oracle
+    steps; flagged bins are recomputed with the GPU's own decisions."""
+    worst, worst_log, resolved = 0.0, 0.0, 0
+    for k in range(pts.n_points):
+        lq, dec = None, None
+        for m, b in enumerate(bins):
+            r = np.asarray(ref_steps[k][m])
+            if near_tie[k][m]:
+                if lq is None:
+                    sub = _reach(w, bins) if sub is None else sub
+                    lq = oracle.line_quantities(w.lines.take(sub), w.species, abundance, float(pts.T_K[k]),
+                                                float(pts.log10_P[k]), float(pts.vturb_kms[k]), w.layout,
+                                                w.options)
+                    dec = gpu_decisions(plan, abundance, pts, k)
+                r = oracle_bin_with_gpu_decisions(lq, w.layout, w.options, b, dec, sub_to_full=sub)
+                resolved += 1
+            worst = max(worst, float(rel_err(got[k][b], r).max()))
+            worst_log = max(worst_log, float(log10_err(got[k][b], r).max()))
+    assert worst <= tol, f"max rel err per step {worst:.3e} > {tol}"
+    return worst, worst_log, resolved
+
+
+def test_served_stream_against_oracle():
+    """Four requests of the serving stream in flight together through
+    odf_submit; each result sampled at 4 points x 16 bins against the
+    oracle (config 4: 1e7 lines, per-request composition and points)."""
+    import torch
+    from paper_2105_13611_amd import odf
+    fx = json.load(open(os.path.join(GOLDEN, "cfg4_served_oracle.json")))
+    w = W.config(4, n_requests=len(fx["requests"]))
+    bins = fx["bins"]
+    for q, r in zip(fx["requests"], w.requests):
+        assert r.points.n_points == q["n_points"]
+        np.testing.assert_array_equal(r.abundance, q["abundance"])
+        pts = r.points.take(np.asarray(q["point_index"]))
+        np.testing.assert_array_equal(pts.T_K, q["T_K"])
+        np.testing.assert_array_equal(pts.log10_P, q["log10_P"])
+    with odf.plan_for(w, precision="mixed", workspace_bytes=WORKSPACE) as plan:
+        tickets = [plan.submit(r.abundance, r.points) for r in w.requests]
+        stats = [plan.wait(t, 600.0) for t, _ in tickets]
+        torch.cuda.synchronize()
+        for st, r in zip(stats, w.requests):
+            assert st["state"] == "DONE", st
+            assert st["points"] == r.points.n_points
+        overlap = any(stats[j]["t_admit"] < stats[i]["t_done"] and stats[i]["t_admit"] < stats[j]["t_done"]
+                      for i in range(len(stats)) for j in range(len(stats)) if i != j)
+        assert overlap, "the requests did not overlap in the loop"
+        worst, worst_log, resolved = 0.0, 0.0, 0
+        for q, r, (t, out) in zip(fx["requests"], w.requests, tickets):
+            idx = np.asarray(q["point_index"])
+            got = out[torch.as_tensor(idx, device=out.device)].double().cpu().numpy()
+            e, el, n = _check_pairs(w, plan, got, q["steps"], q["near_tie"], bins, r.points.take(idx),
+                                    r.abundance, TOL["mixed"])
+            worst, worst_log, resolved = max(worst, e), max(worst_log, el), resolved + n
+    lat = [s["t_done"] - s["t_submit"] for s in stats]
+    print(f"served config 4: {len(stats)} requests ({sum(s['points'] for s in stats)} points), "
+          f"max rel err per step {worst:.3e}, max |dlog10 k| {worst_log:.3e}, near-tie bins {resolved}, "
+          f"latencies {[round(x, 2) for x in lat]} s")
+
+
+@pytest.fixture(scope="module")
+def cfg5():
+    w = W.config(5, n_requests=1)
+    assert w.lines.n_lines == 100_000_000 and w.species.n_stages == 3
+    return w
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_large_line_list_sampled_parity(cfg5, prec):
+    """The 1e8-line list over 80 species x 3 stages with a request's own
+    composition: 4 points of the 57 x 25 x 5 grid x 8 bins, both
+    precisions, against the stored oracle steps."""
+    import torch
+    from paper_2105_13611_amd import odf
+    fx = json.load(open(os.path.join(GOLDEN, "cfg5_sampled_oracle.json")))
+    w = cfg5
+    a = w.requests[0].abundance
+    np.testing.assert_array_equal(a, fx["abundance"])
+    pts = W.Points(np.array(fx["T_K"]), np.array(fx["log10_P"]), np.array(fx["vturb_kms"]))
+    with odf.plan_for(w, precision=prec, workspace_bytes=WORKSPACE) as plan:
+        out, st = plan.compute(a, pts)
+        got = out.double().cpu().numpy()
+        torch.cuda.synchronize()
+        worst, worst_log, resolved = _check_pairs(w, plan, got, fx["steps"], fx["near_tie"], fx["bins"], pts, a,
+                                                  TOL[prec])
+    print(f"1e8 lines {prec}: max rel err per step {worst:.3e}, max |dlog10 k| {worst_log:.3e}, "
+          f"near-tie bins {resolved}, survivors {st['survivors']}, samples {st['voigt_samples']}")
+    assert st["line_evals"] == pts.n_points * 100_000_000
     assert np.all(np.isfinite(got)) and np.all(got > 0)

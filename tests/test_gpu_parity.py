@@ -122,10 +122,9 @@ def test_end_to_end_cfg1(plans1, cfg1, prec):
     w = cfg1
     out, st = plans1[prec].compute(w.species.abundance, w.points)
     out = out.double().cpu().numpy()
-    worst, worst_log, skipped = compare_points(w, out, prec)
+    worst, worst_log, resolved = compare_points(w, out, prec, plan=plans1[prec])
     print(f"cfg1 {prec}: max rel err per step {worst:.3e}, max |dlog10 k| {worst_log:.3e}, "
-          f"ambiguous bins skipped {skipped}; stats {st}")
-    assert skipped <= 1
+          f"bins with near-tie decisions (checked with the GPU's decisions) {resolved}; stats {st}")
     assert worst <= TOL_STEP[prec]
     _, cnt, _ = oracle.odf_point(w.lines, w.species, w.species.abundance, 5000.0, 4.0, 2.0, w.layout,
                                  w.options, bins=[0])
@@ -152,9 +151,8 @@ def test_end_to_end_multi_tile_multi_point(odf, multi, prec):
     with odf.plan_for(w, precision=prec, workspace_bytes=24 << 20) as plan:
         out, st = plan.compute(w.species.abundance, w.points)
         out = out.double().cpu().numpy()
-    worst, worst_log, skipped = compare_points(w, out, prec)
-    print(f"multi {prec}: max rel err {worst:.3e}, max |dlog10 k| {worst_log:.3e}, skipped {skipped}")
-    assert skipped <= 2
+        worst, worst_log, resolved = compare_points(w, out, prec, plan=plan)
+    print(f"multi {prec}: max rel err {worst:.3e}, max |dlog10 k| {worst_log:.3e}, near-tie bins {resolved}")
     assert worst <= TOL_STEP[prec]
 
 
@@ -172,10 +170,9 @@ def test_end_to_end_three_stages_request_composition(odf, prec):
     with odf.plan_for(w, precision=prec, workspace_bytes=64 << 20) as plan:
         out, st = plan.compute(a, w.points)
         out = out.double().cpu().numpy()
-    worst, worst_log, skipped = compare_points(w, out, prec, abundance=a)
+        worst, worst_log, resolved = compare_points(w, out, prec, abundance=a, plan=plan)
     print(f"three stages {prec}: max rel err {worst:.3e}, max |dlog10 k| {worst_log:.3e}, "
-          f"skipped {skipped}, survivors {st['survivors']}")
-    assert skipped <= 2
+          f"near-tie bins {resolved}, survivors {st['survivors']}")
     assert worst <= TOL_STEP[prec]
 
 
@@ -218,8 +215,8 @@ def test_edge_layout_tiny_and_huge_bins(odf, prec):
     with odf.plan_for(w, precision=prec, workspace_bytes=64 << 20) as plan:
         out, _ = plan.compute(w.species.abundance, w.points)
         out = out.double().cpu().numpy()
-    worst, _, skipped = compare_points(w, out, prec)
-    assert skipped == 0 and worst <= TOL_STEP[prec]
+        worst, _, _ = compare_points(w, out, prec, plan=plan)
+    assert worst <= TOL_STEP[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -229,7 +226,7 @@ def test_degenerate_no_survivors_and_empty_list(odf, cfg1, prec):
     with odf.plan_for(w, precision=prec, workspace_bytes=64 << 20) as plan:
         out, st = plan.compute(tiny, w.points)
         assert st["survivors"] == 0
-        worst, _, _ = compare_points(w, out.double().cpu().numpy(), prec, abundance=tiny)
+        worst, _, _ = compare_points(w, out.double().cpu().numpy(), prec, abundance=tiny, plan=plan)
         assert worst <= TOL_STEP[prec]
     empty = replace(w, lines=w.lines.take(np.arange(0)))
     with odf.plan_for(empty, precision=prec, workspace_bytes=64 << 20) as plan:
@@ -247,5 +244,5 @@ def test_options_cutoff_and_cap(odf, multi):
                 points=multi.points.take(np.array([1, 3])))
     with odf.plan_for(w, precision="fp64", workspace_bytes=64 << 20) as plan:
         out, _ = plan.compute(w.species.abundance, w.points)
-    worst, _, skipped = compare_points(w, out.double().cpu().numpy(), "fp64")
-    assert skipped <= 1 and worst <= TOL_STEP["fp64"]
+        worst, _, _ = compare_points(w, out.double().cpu().numpy(), "fp64", plan=plan)
+    assert worst <= TOL_STEP["fp64"]

@@ -50,10 +50,9 @@ def test_random_workload_parity(odf, seed, prec):
     with odf.plan_for(w, precision=prec, workspace_bytes=64 << 20) as plan:
         out, st = plan.compute(w.species.abundance, w.points)
         out = out.double().cpu().numpy()
-    worst, worst_log, skipped = compare_points(w, out, prec)
+        worst, worst_log, resolved = compare_points(w, out, prec, plan=plan)
     o = w.options
     print(f"seed {seed} {prec}: {w.lines.n_lines} lines, {w.layout.n_bins} bins x {w.layout.n_steps} steps, "
           f"cutoff {o.cutoff:g}, cap {o.window_cap_doppler:g}, {o.mean}, {o.electrons}, "
-          f"{w.points.n_points} points: max rel err {worst:.3e}, skipped {skipped}")
-    assert skipped <= 1
+          f"{w.points.n_points} points: max rel err {worst:.3e}, near-tie bins {resolved}")
     assert worst <= TOL_STEP[prec]

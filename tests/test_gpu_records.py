@@ -1,0 +1,137 @@
+"""Stage check of the mixed path's FP32 survivor records against the oracle.
+
+The Voigt kernel of the mixed path trusts, per kept line and point, a
+48-byte record: the nearest grid index J of the centre and the offset phi,
+the window, c1 = sigma ln q / b, the far-wing fraction
+S H ~ (A v + B) / (v^2 + E) with v = u^2 + D, u = sigma x, the strength S,
+the damping a and the packed half-widths of the zones where |x| < 15 and
+|x| < 6 may occur.  Every field is recomputed here from the oracle's S, a,
+b and fractional centre index (Sec. 2.1, eq. l_nu_line; App. E grid), and
+two properties tie them to the oracle's definitions:
+  * beyond each zone half-width, |x| (the oracle's exact x from the index)
+    is at least the zone's radius;
+  * the fraction equals the oracle's S H(x, a) (scipy's Faddeeva function)
+    within the two-node rule's bound 5e-5 wherever |x + i a| >= 15, and in
+    the Lorentz limit (a >= 1e4) within 1/(2 a^2).
+Lines with very large damping are added so that the Lorentz limit is
+exercised."""
+import math
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_13611_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+POINTS = W.Points(np.array([5000.0, 2000.0, 200000.0, 20000.0]), np.array([4.0, 8.0, -4.0, 6.0]),
+                  np.array([2.0, 0.0, 8.0, 4.0]))
+SQRT_PI = math.sqrt(math.pi)
+
+
+@pytest.fixture(scope="module")
+def work():
+    w = W.config(1)
+    L = w.lines
+    g_vdw = L.log_g_vdw.copy()
+    g_vdw[::10] += 4.0            # a tenth of the lines with a >= 1e4 at high pressure
+    lines = replace(L, log_g_vdw=g_vdw)
+    return replace(w, lines=lines, points=POINTS, options=replace(w.options, precision="mixed"))
+
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def _zone(R, c1):
+    """Expected zone half-width from the definition: ceil(1.02 R / c1) + 2
+    fine points, capped to 16 bits; with whether the ceiling is a tie."""
+    v = R * 1.02 / c1
+    return np.minimum(np.ceil(v) + 2, 32767), np.abs(v - np.round(v)) < 1e-9
+
+
+def _x(lq, i, j):
+    lnq = math.log1p(1.0 / 5e5)
+    return np.expm1((lq["jstar"][i] - j) * lnq) / lq["b"][i]
+
+
+def test_fp32_records_against_the_oracle(work):
+    import torch
+    from paper_2105_13611_amd import odf
+    w = work
+    lnq = math.log1p(1.0 / w.layout.resolving_power)
+    n_lorentz = 0
+    with odf.plan_for(w, precision="mixed", workspace_bytes=64 << 20) as plan:
+        for p in range(w.points.n_points):
+            print(f"[records] point {p}: T={w.points.T_K[p]} logP={w.points.log10_P[p]}", flush=True)
+            rec, wz = plan.stage_records(w.species.abundance, w.points, p)
+            sl = plan.stage_lines(w.species.abundance, w.points, p)
+            torch.cuda.synchronize()
+            lq = oracle.line_quantities(w.lines, w.species, w.species.abundance, float(w.points.T_K[p]),
+                                        float(w.points.log10_P[p]), float(w.points.vturb_kms[p]), w.layout,
+                                        w.options)
+            n = rec.size
+            assert n == sl["n_surv"] and n > 100
+            o = sl["orig"]
+            np.testing.assert_array_equal(rec["jlo"], sl["jlo"])
+            np.testing.assert_array_equal(rec["jhi"], sl["jhi"])
+            # the (J, zones) array read beside the windows repeats the record's
+            np.testing.assert_array_equal(wz[:, 0], rec["J"])
+            np.testing.assert_array_equal(wz[:, 1], rec["czh"])
+            S, a, b, js = lq["S"][o], lq["a"][o], lq["b"][o], lq["jstar"][o]
+            # centre: J the nearest index, phi the rest
+            half_tie = np.abs(np.abs(js - np.rint(js)) - 0.5) < 1e-9
+            assert np.all((rec["J"] == np.rint(js)) | half_tie)
+            assert np.max(np.abs(rec["phi"] - (js - rec["J"]))) < 2e-7
+            np.testing.assert_allclose(rec["S"], _f32(S), rtol=1e-6)
+            np.testing.assert_allclose(rec["y"], _f32(a), rtol=1e-6)
+            lor = a >= 1e4
+            n_lorentz += int(lor.sum())
+            c1 = lnq / b
+            # two-node pair C1 (u^2 + a^2 + 1/2) / ((u^2 + a^2 - 1/2)^2 + 2 a^2), u = x
+            t = ~lor
+            C1 = S * a / SQRT_PI
+            np.testing.assert_allclose(rec["c1"][t], _f32(c1[t]), rtol=1e-6)
+            np.testing.assert_allclose(rec["A"][t], _f32(C1[t]), rtol=1e-6)
+            np.testing.assert_allclose(rec["B"][t], _f32(C1[t]), rtol=1e-6)
+            np.testing.assert_allclose(rec["D"][t], _f32(a[t] ** 2 - 0.5), rtol=1e-6, atol=1e-7)
+            np.testing.assert_allclose(rec["E"][t], _f32(2.0 * a[t] ** 2), rtol=1e-6)
+            # Lorentz limit in u = x / a: (S a / sqrt(pi) / a^2) / (u^2 + 1)
+            np.testing.assert_allclose(rec["c1"][lor], _f32(c1[lor] / a[lor]), rtol=1e-6)
+            np.testing.assert_allclose(rec["A"][lor], _f32(C1[lor] / a[lor] ** 2), rtol=1e-6)
+            assert np.all(rec["B"][lor] == 0) and np.all(rec["D"][lor] == 1) and np.all(rec["E"][lor] == 0)
+            # zone half-widths, unpacked (signed 16-bit halves)
+            far = (rec["czh"] & 0xFFFF).astype(np.int16).astype(np.int64)
+            ring = (rec["czh"] >> 16).astype(np.int16).astype(np.int64)
+            for R, got in ((15.0, far), (6.0, ring)):
+                exp, tie = _zone(R, c1)
+                inside = a < R
+                assert np.all(got[~inside] == -32768)
+                ok = (got[inside] == exp[inside]) | (tie[inside] & (np.abs(got[inside] - exp[inside]) <= 1))
+                assert ok.all(), f"zone |x| < {R}: {np.nonzero(~ok)[0][:5]}"
+                # the zone's meaning: from J +- half-width outward, |x| >= R
+                ii = np.nonzero(inside & (got < 32767))[0]
+                for sgn in (-1, 1):
+                    x = _x(lq, o[ii], rec["J"][ii] + sgn * got[ii])
+                    assert np.all(np.abs(x) >= R), f"|x| < {R} outside the zone: {np.min(np.abs(x))}"
+            # the far-wing fraction against the oracle's S H(x, a)
+            for xs in (15.0, 22.5, 40.0, 150.0, 1e3):
+                for sgn in (-1.0, 1.0):
+                    x = sgn * np.sqrt(np.maximum(xs * xs - a * a, 0.0))   # |x + i a| = xs where possible
+                    m = t & (np.hypot(x, a) >= 15.0 - 1e-9)
+                    u = x[m]
+                    v = u * u + rec["D"][m]
+                    f = (rec["A"][m] * v + rec["B"][m]) / (v * v + rec["E"][m])
+                    ref = S[m] * oracle.voigt_h(x[m], a[m])
+                    assert np.max(np.abs(f / ref - 1.0)) < 5e-5 + 3e-6
+            if lor.any():
+                for xm in (0.0, 1.0, 10.0):
+                    x = xm * a[lor]
+                    u = x / a[lor]
+                    f = rec["A"][lor] / (u * u + 1.0)
+                    ref = S[lor] * oracle.voigt_h(x, a[lor])
+                    assert np.all(np.abs(f / ref - 1.0) < 1.0 / (2.0 * a[lor] ** 2) + 3e-6)
+    print(f"[records] Lorentz-limit records checked: {n_lorentz}")
+    assert n_lorentz > 0
