@@ -189,6 +189,24 @@ typedef struct {
   char msg[128];
 } odf_stats;
 
+/* State of a plan's request loop (odf_loop_status).  The workspace is the
+ * loop's byte pool; a request reserves its footprint (odf_request_footprint)
+ * from it when admitted and releases it when final.
+ *   pool_bytes              the pool (the workspace, rounded down to 256 B)
+ *   resident_bytes          bytes reserved by the admitted requests now
+ *   peak_resident_bytes     the most ever reserved at once
+ *   resident_requests       admitted and not yet final
+ *   peak_resident_requests  the most ever resident at once
+ *   queued_requests         submitted, waiting for room
+ *   batches_in_flight       batches on the device now
+ *   slot_points             points per batch slot of a request of that many points or more
+ *   slots_per_request       batch slots a request reserves (at most) */
+typedef struct {
+  int64_t pool_bytes, resident_bytes, peak_resident_bytes;
+  int32_t resident_requests, peak_resident_requests, queued_requests, batches_in_flight;
+  int32_t slot_points, slots_per_request;
+} odf_loop_info;
+
 typedef struct odf_plan_s odf_plan_t;
 
 /* Build a plan: validates and copies every host array, sorts the lines by
@@ -213,7 +231,15 @@ odf_status odf_compute(odf_plan_t *plan, const odf_request *req, odf_stats *stat
 
 /* Queue a request for the plan's request loop and return at once.  The host
  * arrays are copied; req->out must stay valid until the ticket is final.
- * ODF_E_NOMEM if the request can never fit the workspace. */
+ * The request's device work is ordered after the work queued on
+ * options.stream when it is submitted (req->out may have been allocated
+ * there).  Admission is by HBM footprint: the workspace is a byte pool, and
+ * the oldest waiting request is admitted as soon as its footprint
+ * (odf_request_footprint: up to two batch slots of min(n_points, 16)
+ * points) fits the free bytes; it keeps them until it is final, and later
+ * requests never overtake it.  Resident requests take turns handing one
+ * batch each to the device.  ODF_E_NOMEM if the footprint exceeds the whole
+ * pool, so that the request could never be admitted. */
 odf_status odf_submit(odf_plan_t *plan, const odf_request *req, int64_t *ticket);
 
 /* Non-blocking status of a ticket; DONE and FAILED are final. */
@@ -233,8 +259,13 @@ int64_t odf_grid_points(const odf_layout *layout);
 /* Workspace bytes that one point occupies while it is being processed. */
 int64_t odf_point_footprint(const odf_plan_t *plan);
 
-/* Workspace bytes the request loop reserves for a request of n_points. */
+/* Workspace bytes the request loop reserves for a request of n_points
+ * while it is resident (0 for no points, -1 for a NULL plan). */
 int64_t odf_request_footprint(const odf_plan_t *plan, int32_t n_points);
+
+/* Current and peak occupancy of the request loop's pool (odf_loop_info).
+ * ODF_E_INVALID for a NULL argument. */
+odf_status odf_loop_status(odf_plan_t *plan, odf_loop_info *out);
 
 /* Message of the last error on this thread ("" if none). */
 const char *odf_last_error(void);

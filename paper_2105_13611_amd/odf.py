@@ -73,6 +73,16 @@ class OdfStats(C.Structure):
                     voigt_samples=self.voigt_samples, msg=self.msg.decode(errors="replace"))
 
 
+class OdfLoopInfo(C.Structure):
+    _fields_ = [("pool_bytes", C.c_int64), ("resident_bytes", C.c_int64), ("peak_resident_bytes", C.c_int64),
+                ("resident_requests", C.c_int32), ("peak_resident_requests", C.c_int32),
+                ("queued_requests", C.c_int32), ("batches_in_flight", C.c_int32),
+                ("slot_points", C.c_int32), ("slots_per_request", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 #: every function the C ABI exports, with its ctypes signature
 SIGNATURES = {
     "odf_plan": (C.c_int, [C.POINTER(OdfLines), C.POINTER(OdfSpecies), C.POINTER(OdfLayout),
@@ -85,6 +95,7 @@ SIGNATURES = {
     "odf_grid_points": (C.c_int64, [C.POINTER(OdfLayout)]),
     "odf_point_footprint": (C.c_int64, [C.c_void_p]),
     "odf_request_footprint": (C.c_int64, [C.c_void_p, C.c_int32]),
+    "odf_loop_status": (C.c_int, [C.c_void_p, C.POINTER(OdfLoopInfo)]),
     "odf_last_error": (C.c_char_p, []),
     "odf_stage_lines": (C.c_int, [C.c_void_p, C.POINTER(OdfRequest), C.c_int32, _I64, _I64, _I64,
                                   _I32, _I32, _D, _D, _D]),
@@ -259,6 +270,12 @@ class Plan:
 
     def request_footprint(self, n_points: int) -> int:
         return int(lib().odf_request_footprint(self.handle, int(n_points)))
+
+    def loop_status(self):
+        """The request loop's pool occupancy (odf_loop_info as a dict)."""
+        st = OdfLoopInfo()
+        _check(lib().odf_loop_status(self.handle, C.byref(st)))
+        return st.as_dict()
 
     def out_shape(self, n_points):
         """[points][bins][steps] for ODF tables, [points][N] for fine-grid opacity."""

@@ -38,7 +38,9 @@ def served():
     return replace(w, requests=reqs)
 
 
-def _plan(odf, w, slots_points=4, n_slots=3):
+def _plan(odf, w, slots_points=4, n_slots=5):
+    """A plan whose pool holds n_slots batch slots of slots_points points
+    (a request of more than that many points reserves two of them)."""
     probe = odf.plan_for(w, workspace_bytes=256 << 20, max_batch_points=slots_points)
     ws = probe.request_footprint(slots_points) * n_slots + (1 << 20)
     probe.destroy()
@@ -96,14 +98,76 @@ def test_unknown_ticket_invalid_request_and_empty_request(odf, served):
 
 
 def test_footprint_and_admission_bound(odf, served):
+    """Admission by footprint: a request reserves min(n, 4)-point slots, two
+    of them once it has more than one batch; the pool holds five 4-point
+    slots, so small requests are resident together while large ones wait
+    for room.  Sampled while the loop runs, the reserved bytes never exceed
+    the pool, and every result equals the request computed alone."""
+    import time
+    import torch
     w = served
     with _plan(odf, w) as plan:
-        f1, f4, f100 = plan.request_footprint(1), plan.request_footprint(4), plan.request_footprint(100)
-        assert 0 < f1 <= f4 <= f100 <= plan.workspace.numel()
-        # more requests than slots: all complete, in any order, each exactly once
-        tickets = [plan.submit(r.abundance, r.points) for r in w.requests * 2]
-        for t, _ in tickets:
-            assert plan.wait(t, 300.0)["state"] == "DONE"
+        st0 = plan.loop_status()
+        f0, f1, f3, f4, f5, f100 = (plan.request_footprint(n) for n in (0, 1, 3, 4, 5, 100))
+        assert f0 == 0 and 0 < f1 < f3 < f4 and f5 == f100 == 2 * f4
+        assert st0["slot_points"] == 4 and st0["slots_per_request"] == 2
+        pool = st0["pool_bytes"]
+        assert 5 * f4 <= pool < 6 * f4 and pool <= plan.workspace.numel()
+        # requests of 1..18 points, more than fit at once
+        rng = np.random.default_rng(3)
+        reqs = []
+        for k in range(14):
+            r = w.requests[k % len(w.requests)]
+            n = int(rng.integers(1, min(18, r.points.n_points) + 1))
+            reqs.append(W.Request(r.abundance, r.points.take(np.arange(n)), 0.0))
+        alone = [plan.compute(r.abundance, r.points)[0].clone() for r in reqs]
+        tickets = [plan.submit(r.abundance, r.points) for r in reqs]
+        seen = []
+        while True:
+            st = plan.loop_status()
+            seen.append(st)
+            assert st["resident_bytes"] <= pool and st["peak_resident_bytes"] <= pool
+            if all(plan.poll(t)["state"] in ("DONE", "FAILED") for t, _ in tickets):
+                break
+            time.sleep(0.002)
+        torch.cuda.synchronize()
+        stats = [plan.wait(t, 60.0) for t, _ in tickets]
+        for st, (t, out), a, r in zip(stats, tickets, alone, reqs):
+            assert st["state"] == "DONE", st
+            assert bool((out == a).all())
+        end = plan.loop_status()
+    assert end["resident_bytes"] == 0 and end["resident_requests"] == 0 and end["batches_in_flight"] == 0
+    assert 2 <= end["peak_resident_requests"] and end["peak_resident_bytes"] <= pool
+    assert max(s["queued_requests"] for s in seen) > 0       # some waited for room
+    # arrival order: a request is never admitted before an earlier one
+    admits = [s["t_admit"] for s in stats]
+    assert all(admits[i] <= admits[i + 1] for i in range(len(admits) - 1))
+    print(f"pool {pool} B ({pool / f4:.2f} slots of 4 points): peak {end['peak_resident_bytes']} B, "
+          f"{end['peak_resident_requests']} requests resident at most, "
+          f"{max(s['queued_requests'] for s in seen)} queued at most")
+
+
+def test_submit_orders_after_the_callers_stream(odf, served):
+    """A request's device work starts only after what was queued on the
+    plan's stream before submit: here a long chain of products and then a
+    fill of the output buffer with NaN; the result must be the request's,
+    not the fill."""
+    import torch
+    w = served
+    r = w.requests[2]
+    with _plan(odf, w) as plan:
+        ref = plan.compute(r.abundance, r.points)[0].clone()
+        out = plan.new_out(r.points.n_points)
+        a = torch.randn(4096, 4096, device=plan.device)
+        with torch.cuda.stream(plan.stream):
+            for _ in range(40):
+                a = (a @ a).div_(a.abs().max())
+            out.fill_(float("nan"))
+        t, _ = plan.submit(r.abundance, r.points, out)
+        st = plan.wait(t, 300.0)
+        torch.cuda.synchronize()
+    assert st["state"] == "DONE"
+    assert bool((out == ref).all())
 
 
 def test_compute_waits_for_the_loop(odf, served):
