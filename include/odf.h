@@ -284,8 +284,10 @@ odf_status odf_stage_lines(odf_plan_t *plan, const odf_request *req, int32_t poi
                            double *S, double *a, double *b);
 
 /* Survivor records of point `point` of req exactly as this plan's Voigt
- * kernel reads them, in wavelength order (the order of odf_stage_lines),
- * for checking the values the kernel trusts.  MIXED plans: 48-byte FP32
+ * kernel reads them, for checking the values the kernel trusts.  Order: the
+ * *n_narrow survivors whose half-window (the larger side from the nearest
+ * grid index of the centre, plus one) is at most 1024 fine points, then the
+ * others, each class in wavelength order.  MIXED plans: 48-byte FP32
  * records (int32 J = nearest index of the line centre, j_lo, j_hi, packed
  * zone half-widths; float phi = centre - J, c1 = sigma ln q / b, the
  * far-wing fraction S H = (A v + B) / (v^2 + E) with v = u^2 + D and
@@ -301,8 +303,8 @@ odf_status odf_stage_lines(odf_plan_t *plan, const odf_request *req, int32_t poi
  * ODF_E_INVALID when more than `capacity` lines survive (the count is
  * still returned). */
 odf_status odf_stage_records(odf_plan_t *plan, const odf_request *req, int32_t point,
-                             int64_t *n_surv, int32_t *record_bytes, void *rec_host,
-                             int64_t capacity, int32_t *wz_host);
+                             int64_t *n_surv, int64_t *n_narrow, int32_t *record_bytes,
+                             void *rec_host, int64_t capacity, int32_t *wz_host);
 
 /* Gas state of point `point` of req (Sec. 2.1; App. A): state host [4]
  * receives n_e, the heavy-particle density N_heavy = P/kT - n_e (with fixed

@@ -282,6 +282,7 @@ __global__ void k_point_state(Params P, Batch B) {
     ps.pad = 0.0;
     B.state[p] = ps;
     B.hmax[p] = 0;
+    B.hmax_w[p] = 0;
     B.nsamp[p] = 0ull;
     B.nit[p] = iters;
   }
@@ -355,12 +356,28 @@ struct LineEval {
   bool surv;
 };
 
+// The keep test S H(0, a) >= thr with H(0, a) = erfcx(a), decided where
+// possible by the classical bounds of erfcx for a >= 0,
+//   2 / (sqrt(pi) (a + sqrt(a^2 + 2))) < erfcx(a) <= 2 / (sqrt(pi) (a + sqrt(a^2 + 4/pi))),
+// (Abramowitz and Stegun 7.1.13), each with a margin of 1e-13 for its own
+// rounding.  Only lines with thr / U(a) <= S < thr / L(a), a band of at most
+// a factor sqrt(pi/2) = 1.25 in S (at a = 0; it narrows as
+// 1 + (1 - 2/pi) / (2 a^2) for large a), need erfcx itself, so every
+// decision is the one erfcx gives.
+__device__ __forceinline__ bool keep_line(double S, double a, double thr) {
+  if (!(S >= thr)) return false;                  // erfcx(a) <= 1
+  const double lo = 2.0 / (kSqrtPi * (a + sqrt(fma(a, a, 2.0))));
+  if (S * lo >= thr * (1.0 + 1e-13)) return true;
+  const double hi = 2.0 / (kSqrtPi * (a + sqrt(fma(a, a, 4.0 / kPi))));
+  if (S * hi < thr * (1.0 - 1e-13)) return false;
+  return S * erfcx(a) >= thr;
+}
+
 // Strength, damping, selection and window of one line at one point.  The
-// keep test S H(0,a) >= thr is skipped when S < thr already decides it
-// (H(0,a) = erfcx(a) <= 1 for a >= 0), and entirely when the caller already
-// knows the line is kept (kKept: the emission of survivors); the window is
-// computed the same way in both cases.
-template <bool kKept = false>
+// keep test is skipped when the caller already knows the line is kept
+// (kKept); kWindow false leaves the window out (the emission reads the one
+// the selection stored).
+template <bool kKept = false, bool kWindow = true>
 __device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d,
                                               const PointState& ps, const TFactors& tf,
                                               const double* __restrict__ pop,
@@ -378,7 +395,11 @@ __device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d
   if (!kKept && !(S >= thr)) return e;
   const double a = (d.g_rad + d.g_stark * ps.cS + d.g_vdw * ps.cW) / b;
   e.a = a;
-  if (!kKept && !(S * erfcx(a) >= thr)) return e;
+  if (!kKept && !keep_line(S, a, thr)) return e;
+  if (!kWindow) {
+    e.surv = true;
+    return e;
+  }
   const double xg = sqrt(fmax(0.0, log(2.0 * S / thr)));
   const double xl = sqrt(2.0 * S * a / (kSqrtPi * thr));
   const double xw = fmin(P.cap, fmax(xg, xl));
@@ -396,12 +417,13 @@ __device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d
 constexpr int kWavesK1 = kLineBlock / 64;
 
 // Selection: one thread per line, looping over the batch's points so the
-// line's constants are read once per batch.  Writes the keep flags, the
-// per-(point, block) survivor counts, and per point the largest half-window
-// and the number of Voigt samples.
+// line's constants are read once per batch.  Writes the keep flags (1: a
+// narrow survivor, half-window at most kNarrowHalf; 2: a wide one), the
+// per-(point, class, block) survivor counts, and per point each class's
+// largest half-window and the number of Voigt samples.
 __global__ __launch_bounds__(kLineBlock) void k_select(Params P, DevLines L, Batch B) {
-  __shared__ int32_t wc[kMaxBatch][kWavesK1];
-  __shared__ int32_t wh[kMaxBatch][kWavesK1];
+  __shared__ int32_t wc[2][kMaxBatch][kWavesK1];
+  __shared__ int32_t wh[2][kMaxBatch][kWavesK1];
   __shared__ unsigned long long wn[kMaxBatch][kWavesK1];
   const int64_t i = (int64_t)blockIdx.x * kLineBlock + threadIdx.x;
   const int64_t nblk = gridDim.x;
@@ -414,7 +436,7 @@ __global__ __launch_bounds__(kLineBlock) void k_select(Params P, DevLines L, Bat
   const int np = B.n_points;
   for (int p = 0; p < np; ++p) {
     const PointState ps = B.state[p];
-    bool s = false;
+    bool s = false, nar = false;
     int32_t half = 0;
     unsigned long long ns = 0;
     if (valid) {
@@ -422,37 +444,47 @@ __global__ __launch_bounds__(kLineBlock) void k_select(Params P, DevLines L, Bat
       const LineEval e = eval_line(P, d, ps, tf, B.pop + (int64_t)p * P.n_species * P.n_stages,
                                    B.bT + (int64_t)p * P.n_species);
       s = e.surv;
-      B.flags[(int64_t)p * B.rec_stride + i] = s ? 1 : 0;
       if (s) {
         half = max(J - e.jlo, e.jhi - J) + 1;
         ns = (unsigned long long)(e.jhi - e.jlo + 1);
+        nar = half <= kNarrowHalf;
+        B.wline[(int64_t)p * B.rec_stride + i] = make_int2(e.jlo, e.jhi);
       }
+      B.flags[(int64_t)p * B.rec_stride + i] = s ? (nar ? 1 : 2) : 0;
     }
-    const unsigned long long m = __ballot(s);
-    if (m) {
+    const unsigned long long mn = __ballot(s && nar), mw = __ballot(s && !nar);
+    int32_t hn = nar ? half : 0, hw = (s && !nar) ? half : 0;
+    if (mn | mw) {
       for (int o = 32; o > 0; o >>= 1) {
-        half = max(half, __shfl_xor(half, o, 64));
+        hn = max(hn, __shfl_xor(hn, o, 64));
+        hw = max(hw, __shfl_xor(hw, o, 64));
         ns += __shfl_xor(ns, o, 64);
       }
     }
     if (lane == 0) {
-      wc[p][wid] = __popcll(m);
-      wh[p][wid] = half;
+      wc[0][p][wid] = __popcll(mn);
+      wc[1][p][wid] = __popcll(mw);
+      wh[0][p][wid] = hn;
+      wh[1][p][wid] = hw;
       wn[p][wid] = ns;
     }
   }
   __syncthreads();
   for (int p = threadIdx.x; p < np; p += blockDim.x) {
-    int32_t c = 0, h = 0;
+    int32_t cn = 0, cw = 0, hn = 0, hw = 0;
     unsigned long long n = 0;
     for (int w = 0; w < kWavesK1; ++w) {
-      c += wc[p][w];
-      h = max(h, wh[p][w]);
+      cn += wc[0][p][w];
+      cw += wc[1][p][w];
+      hn = max(hn, wh[0][p][w]);
+      hw = max(hw, wh[1][p][w]);
       n += wn[p][w];
     }
-    B.blk[(int64_t)p * nblk + blockIdx.x] = c;
+    B.blk[((int64_t)p * 2 + 0) * nblk + blockIdx.x] = cn;
+    B.blk[((int64_t)p * 2 + 1) * nblk + blockIdx.x] = cw;
     if (n) {
-      atomicMax(B.hmax + p, h);
+      if (hn) atomicMax(B.hmax + p, hn);
+      if (hw) atomicMax(B.hmax_w + p, hw);
       atomicAdd(B.nsamp + p, n);
     }
   }
@@ -466,42 +498,51 @@ hipError_t launch_select(hipStream_t st, const Params& P, const DevLines& L, con
   return hipGetLastError();
 }
 
-// Exclusive scan of the per-block survivor counts of one point (one
-// workgroup of 1024 threads per point, fixed order: deterministic).
+// Exclusive scan of the per-block survivor counts of one point, each class
+// on its own (one workgroup of 1024 threads per point, fixed order:
+// deterministic); the narrow class's total places the wide records after it.
 __global__ __launch_bounds__(1024) void k_scan(Batch B, int64_t nblk) {
   __shared__ int32_t wsum[16];
   __shared__ int32_t carry;
   const int p = blockIdx.x;
-  int32_t* c = B.blk + (int64_t)p * nblk;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int64_t base = 0; base < nblk; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    const int32_t v = (i < nblk) ? c[i] : 0;
-    int32_t x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int32_t t = __shfl_up(x, o, 64);
-      if (lane >= o) x += t;
-    }
-    if (lane == 63) wsum[wid] = x;
+  int32_t total[2] = {0, 0};
+  for (int cls = 0; cls < 2; ++cls) {
+    int32_t* c = B.blk + ((int64_t)p * 2 + cls) * nblk;
+    if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int32_t run = 0;
-      for (int w = 0; w < 16; ++w) {
-        const int32_t t = wsum[w];
-        wsum[w] = run;
-        run += t;
+    for (int64_t base = 0; base < nblk; base += 1024) {
+      const int64_t i = base + threadIdx.x;
+      const int32_t v = (i < nblk) ? c[i] : 0;
+      int32_t x = v;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int32_t t = __shfl_up(x, o, 64);
+        if (lane >= o) x += t;
       }
+      if (lane == 63) wsum[wid] = x;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int w = 0; w < 16; ++w) {
+          const int32_t t = wsum[w];
+          wsum[w] = run;
+          run += t;
+        }
+      }
+      __syncthreads();
+      const int32_t excl = carry + wsum[wid] + x - v;
+      if (i < nblk) c[i] = excl;
+      __syncthreads();
+      if (threadIdx.x == 1023) carry = excl + v;
+      __syncthreads();
     }
-    __syncthreads();
-    const int32_t excl = carry + wsum[wid] + x - v;
-    if (i < nblk) c[i] = excl;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry = excl + v;
+    total[cls] = carry;
     __syncthreads();
   }
-  if (threadIdx.x == 0) B.nsurv[p] = carry;
+  if (threadIdx.x == 0) {
+    B.nsurv[p] = total[0] + total[1];
+    B.nsurv_n[p] = total[0];
+  }
 }
 
 hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const Batch& B) {
@@ -517,18 +558,23 @@ hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const
 // per line, looping over the batch's points.
 template <bool kRec64>
 __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch B) {
-  __shared__ int32_t wc[kMaxBatch][kWavesK1];
+  __shared__ int32_t wc[2][kMaxBatch][kWavesK1];
   const int64_t i = (int64_t)blockIdx.x * kLineBlock + threadIdx.x;
   const int64_t nblk = gridDim.x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const bool valid = i < L.n;
   const int np = B.n_points;
   unsigned long long mine = 0;   // bit p: this line survives at point p
+  unsigned long long wide = 0;   // bit p: ... in the wide class
   for (int p = 0; p < np; ++p) {
-    const bool f = valid && B.flags[(int64_t)p * B.rec_stride + i];
+    const uint8_t f = valid ? B.flags[(int64_t)p * B.rec_stride + i] : (uint8_t)0;
     if (f) mine |= 1ull << p;
-    const unsigned long long m = __ballot(f);
-    if (lane == 0) wc[p][wid] = __popcll(m);
+    if (f == 2) wide |= 1ull << p;
+    const unsigned long long mn = __ballot(f == 1), mw = __ballot(f == 2);
+    if (lane == 0) {
+      wc[0][p][wid] = __popcll(mn);
+      wc[1][p][wid] = __popcll(mw);
+    }
   }
   __syncthreads();
   if (!__ballot(mine != 0ull)) return;
@@ -538,16 +584,21 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int p = 0; p < np; ++p) {
     const bool f = (mine >> p) & 1ull;
-    const unsigned long long m = __ballot(f);
-    if (!m) continue;
+    const int cls = (int)((wide >> p) & 1ull);
+    const unsigned long long mn = __ballot(f && cls == 0), mw = __ballot(f && cls == 1);
+    if (!(mn | mw)) continue;
     if (!f) continue;
-    int32_t off = B.blk[(int64_t)p * nblk + blockIdx.x];
-    for (int w = 0; w < wid; ++w) off += wc[p][w];
-    off += __popcll(m & below);
+    int32_t off = B.blk[((int64_t)p * 2 + cls) * nblk + blockIdx.x];
+    for (int w = 0; w < wid; ++w) off += wc[cls][p][w];
+    off += __popcll((cls ? mw : mn) & below);
+    if (cls) off += B.nsurv_n[p];
     const PointState ps = B.state[p];
     tf.update(d, ps.T);
-    const LineEval e = eval_line<true>(P, d, ps, tf, B.pop + (int64_t)p * P.n_species * P.n_stages,
-                                       B.bT + (int64_t)p * P.n_species);
+    LineEval e = eval_line<true, false>(P, d, ps, tf, B.pop + (int64_t)p * P.n_species * P.n_stages,
+                                        B.bT + (int64_t)p * P.n_species);
+    const int2 wl = B.wline[(int64_t)p * B.rec_stride + i];
+    e.jlo = wl.x;
+    e.jhi = wl.y;
     const double Jd = rint(d.j0s);
     const int32_t J = (int32_t)Jd;
     const int64_t slot = (int64_t)p * B.rec_stride + off;

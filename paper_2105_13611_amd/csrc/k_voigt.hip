@@ -452,30 +452,41 @@ __global__ __launch_bounds__(256, 6) void k_voigt32(Params P, Batch B,
   const int2* __restrict__ win = B.win + pt * B.rec_stride;
   const int2* __restrict__ wz = B.wz + pt * B.rec_stride;
   const int ns = B.nsurv[pt];
-  const int H = B.hmax[pt];
+  const int nn = B.nsurv_n[pt];
   const float lnq = (float)P.lnq;
   const float lnq2 = lnq * 0.5f, lnq6 = lnq * lnq * (1.0f / 6.0f);
   const float q64 = (float)exp(-64.0 * P.lnq);              // nu(j + 64) / nu(j)
   const float g64 = (float)(expm1(-64.0 * P.lnq) / P.lnq);  // (q^-64 - 1) / ln q
-  const int c0 = lower_bound_J(rec, ns, t_lo - H);
-  const int c1 = upper_bound_J(rec, ns, t_hi + H);
   int since_flush = 0;
+  // the narrow class, then the wide one, each scanned over the records whose
+  // centres lie within that class's largest half-window of the tile: one
+  // loop over a virtual index v that runs through both ranges, record
+  // c0n + v below n1 and c0n + v + shift from there on
+  const int Hn = B.hmax[pt], Hw = B.hmax_w[pt];
+  const int c0n = lower_bound_J(rec, nn, t_lo - Hn), c1n = upper_bound_J(rec, nn, t_hi + Hn);
+  const int c0w = nn + lower_bound_J(rec + nn, ns - nn, t_lo - Hw);
+  const int c1w = nn + upper_bound_J(rec + nn, ns - nn, t_hi + Hw);
+  const int n1 = c1n - c0n, nv = n1 + (c1w - c0w);
+  const int shift = c0w - c0n - n1;
   // the windows of 64 records (from the compact window array), one per
   // lane, the next 64 prefetched while these are summed; each intersecting
   // record is then read with scalar loads
   // (lanes past the end hold an empty window that meets no tile)
   const int2 none = make_int2(0x3fffffff, -0x3fffffff);
   int2 nxt = none, nxz = make_int2(0, 0);
-  if (c0 + lane < c1) {
-    nxt = win[c0 + lane];
-    nxz = wz[c0 + lane];
+  if (lane < nv) {
+    const int r = c0n + lane + (lane >= n1 ? shift : 0);
+    nxt = win[r];
+    nxz = wz[r];
   }
-  for (int base = c0; base < c1; base += 64) {
+  for (int vb = 0; vb < nv; vb += 64) {
     const int2 cur = nxt, cz = nxz;
     nxt = none;
-    if (base + 64 + lane < c1) {
-      nxt = win[base + 64 + lane];
-      nxz = wz[base + 64 + lane];
+    const int vn = vb + 64 + lane;
+    if (vn < nv) {
+      const int r = c0n + vn + (vn >= n1 ? shift : 0);
+      nxt = win[r];
+      nxz = wz[r];
     }
     unsigned long long m = __ballot(cur.x <= t_hi && cur.y >= t_lo);
     if (!m) continue;
@@ -489,12 +500,14 @@ __global__ __launch_bounds__(256, 6) void k_voigt32(Params P, Batch B,
     while (mf) {
       const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(mf));
       mf &= mf - 1;
-      far_field32(load_rec32(rec + base + k), t_lo, lane, lnq2, lnq6, Q, lfs, lfc);
+      const int r = c0n + vb + k + (vb + k >= n1 ? shift : 0);
+      far_field32(load_rec32(rec + r), t_lo, lane, lnq2, lnq6, Q, lfs, lfc);
     }
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(m));
       m &= m - 1;
-      line32(load_rec32(rec + base + k), __builtin_amdgcn_readlane(fm, k),
+      const int r = c0n + vb + k + (vb + k >= n1 ? shift : 0);
+      line32(load_rec32(rec + r), __builtin_amdgcn_readlane(fm, k),
              __builtin_amdgcn_readlane(nc, k), t_lo, lane, lnq2, lnq6, q64, g64, Q, lds_ser, p);
       if (++since_flush == kFlushLines) {
         flush32(s, p, lc, lane);
@@ -732,25 +745,33 @@ __global__ __launch_bounds__(256, 4) void k_voigt64(Params P, Batch B, const Qua
   const Rec64* __restrict__ rec = reinterpret_cast<const Rec64*>(B.rec) + p * B.rec_stride;
   const int2* __restrict__ win = B.win + p * B.rec_stride;
   const int ns = B.nsurv[p];
-  const int H = B.hmax[p];
+  const int nn = B.nsurv_n[p];
   const double lnq = P.lnq;
   const double q64 = exp(-64.0 * lnq);              // nu(j + 64) / nu(j)
   const double g64 = expm1(-64.0 * lnq) / lnq;      // (q^-64 - 1) / ln q
-  const int c0 = lower_bound_J(rec, ns, t_lo - H);
-  const int c1 = upper_bound_J(rec, ns, t_hi + H);
+  // the narrow class, then the wide one (one loop over both ranges, as in
+  // k_voigt32)
+  const int Hn = B.hmax[p], Hw = B.hmax_w[p];
+  const int c0n = lower_bound_J(rec, nn, t_lo - Hn), c1n = upper_bound_J(rec, nn, t_hi + Hn);
+  const int c0w = nn + lower_bound_J(rec + nn, ns - nn, t_lo - Hw);
+  const int c1w = nn + upper_bound_J(rec + nn, ns - nn, t_hi + Hw);
+  const int n1 = c1n - c0n, nv = n1 + (c1w - c0w);
+  const int shift = c0w - c0n - n1;
   // windows one per lane (next 64 prefetched), records by scalar loads
   const int2 none = make_int2(0x7fffffff, -0x7fffffff - 1);
   int2 nxt = none;
-  if (c0 + lane < c1) nxt = win[c0 + lane];
-  for (int base = c0; base < c1; base += 64) {
+  if (lane < nv) nxt = win[c0n + lane + (lane >= n1 ? shift : 0)];
+  for (int vb = 0; vb < nv; vb += 64) {
     const int2 cur = nxt;
     nxt = none;
-    if (base + 64 + lane < c1) nxt = win[base + 64 + lane];
+    const int vn = vb + 64 + lane;
+    if (vn < nv) nxt = win[c0n + vn + (vn >= n1 ? shift : 0)];
     unsigned long long m = __ballot(cur.x <= t_hi && cur.y >= t_lo);
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);
       m &= m - 1;
-      line64(load_rec64(rec + base + k), t_lo, t_hi, lane, lnq, q64, g64, Q, as, ls);
+      const int r = c0n + vb + k + (vb + k >= n1 ? shift : 0);
+      line64(load_rec64(rec + r), t_lo, t_hi, lane, lnq, q64, g64, Q, as, ls);
     }
   }
   double* kap = reinterpret_cast<double*>(B.kappa) + p * B.kappa_stride;

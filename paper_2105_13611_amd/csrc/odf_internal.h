@@ -26,6 +26,13 @@ constexpr int kWavePoints = kWave * kRows;       // 1024 fine points per wave
 constexpr int kWavesPerWG = 4;
 constexpr int kWGPoints = kWavePoints * kWavesPerWG;  // 4096 per workgroup
 constexpr int kLineBlock = 256;                  // lines per workgroup in K1
+// Survivors are emitted in two classes by half-window (the larger of the
+// two sides, in fine points): narrow (at most kNarrowHalf) first, then wide,
+// each class in wavelength order.  A Voigt wave scans each class only
+// within that class's largest half-window of its tile, so the thousands of
+// narrow lines around a tile are not scanned out to the reach of the few
+// capped lines whose windows span thousands of points.
+constexpr int kNarrowHalf = 1024;
 constexpr int kMaxBatch = 64;                    // points per device batch (bit masks in K1)
 
 // ---- Voigt region constants -----------------------------------------------
@@ -129,7 +136,8 @@ struct PointState {
   double pad;
 };
 
-// Survivor records, one per kept line and point, in wavelength order.  A
+// Survivor records, one per kept line and point: the narrow class, then the
+// wide one, each in wavelength order (kNarrowHalf).  A
 // wave loads the windows of 64 of them at a time (one per lane; for FP32
 // records also their (J, czh), from which each lane computes its record's
 // row masks), tests them against its tile with one ballot and reads each
@@ -178,10 +186,13 @@ struct Batch {
   PointState* state;    // [B]
   double* pop;          // [B][S*K]
   double* bT;           // [B][S]
-  uint8_t* flags;       // [B][L]
-  int32_t* blk;         // [B][nblk]   counts, then offsets
-  int32_t* nsurv;       // [B]
-  int32_t* hmax;        // [B]         max half-window in fine points
+  uint8_t* flags;       // [B][L]       0: dropped, 1: narrow survivor, 2: wide survivor
+  int2* wline;          // [B][L]       survivors' windows (j_lo, j_hi) by line, from the selection
+  int32_t* blk;         // [B][2][nblk] counts per class, then offsets within the class
+  int32_t* nsurv;       // [B]         survivors (both classes)
+  int32_t* nsurv_n;     // [B]         narrow survivors (the first nsurv_n records)
+  int32_t* hmax;        // [B]         max half-window of the narrow class, in fine points
+  int32_t* hmax_w;      // [B]         max half-window of the wide class
   unsigned long long* nsamp;  // [B]
   int32_t* nit;         // [B]         ionisation-equilibrium steps (0: fixed P_e; < 0: not converged)
   void* rec;            // [B][L] Rec32 or Rec64

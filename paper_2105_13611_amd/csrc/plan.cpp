@@ -216,9 +216,12 @@ SlotLayout make_slot(const odf_plan_s* p, int32_t pts) {
   s.off_pop = take(8 * S * K * pts);
   s.off_bT = take(8 * S * pts);
   s.off_flags = take(std::max<int64_t>(L, 1) * pts);
-  s.off_blk = take(4 * std::max<int64_t>(nblk, 1) * pts);
+  s.off_wline = take((int64_t)sizeof(int2) * std::max<int64_t>(L, 1) * pts);
+  s.off_blk = take(4 * 2 * std::max<int64_t>(nblk, 1) * pts);
   s.off_nsurv = take(4 * pts);
+  s.off_nsurv_n = take(4 * pts);
   s.off_hmax = take(4 * pts);
+  s.off_hmax_w = take(4 * pts);
   s.off_nsamp = take(8 * pts);
   s.off_nit = take(4 * pts);
   s.off_rec = take((mixed ? (int64_t)sizeof(Rec32) : (int64_t)sizeof(Rec64)) * std::max<int64_t>(L, 1) * pts);
@@ -242,9 +245,12 @@ Batch make_batch(const odf_plan_s* p, const SlotLayout& s, char* base, int32_t n
   B.pop = reinterpret_cast<double*>(base + s.off_pop);
   B.bT = reinterpret_cast<double*>(base + s.off_bT);
   B.flags = reinterpret_cast<uint8_t*>(base + s.off_flags);
+  B.wline = reinterpret_cast<int2*>(base + s.off_wline);
   B.blk = reinterpret_cast<int32_t*>(base + s.off_blk);
   B.nsurv = reinterpret_cast<int32_t*>(base + s.off_nsurv);
+  B.nsurv_n = reinterpret_cast<int32_t*>(base + s.off_nsurv_n);
   B.hmax = reinterpret_cast<int32_t*>(base + s.off_hmax);
+  B.hmax_w = reinterpret_cast<int32_t*>(base + s.off_hmax_w);
   B.nsamp = reinterpret_cast<unsigned long long*>(base + s.off_nsamp);
   B.nit = reinterpret_cast<int32_t*>(base + s.off_nit);
   B.rec = base + s.off_rec;
@@ -862,6 +868,9 @@ odf_status odf_stage_lines(odf_plan_t* p, const odf_request* r, int32_t point, i
   }
   (void)hipFree(rec);
   if (st != ODF_OK) return st;
+  // the kernel's order is the narrow class, then the wide one: report the
+  // survivors in wavelength order (sorted line index)
+  std::sort(h.begin(), h.begin() + ns, [](const Rec64& x, const Rec64& y) { return x.li < y.li; });
   *n_surv = ns;
   *voigt_samples = (int64_t)nsamp;
   for (int i = 0; i < ns; ++i) {
@@ -876,14 +885,15 @@ odf_status odf_stage_lines(odf_plan_t* p, const odf_request* r, int32_t point, i
 }
 
 odf_status odf_stage_records(odf_plan_t* p, const odf_request* r, int32_t point, int64_t* n_surv,
-                             int32_t* record_bytes, void* rec_host, int64_t capacity, int32_t* wz_host) {
+                             int64_t* n_narrow, int32_t* record_bytes, void* rec_host, int64_t capacity,
+                             int32_t* wz_host) {
   g_err.clear();
   if (!p) { set_error("plan is NULL"); return ODF_E_INVALID; }
   odf_status st = validate_request(p, r, false);
   if (st != ODF_OK) return st;
   if (point < 0 || point >= r->n_points) { set_error("point %d out of range", point); return ODF_E_INVALID; }
   const bool mixed = p->opts.precision == ODF_PREC_MIXED;
-  if (!n_surv || !record_bytes || !rec_host || (mixed && !wz_host)) {
+  if (!n_surv || !n_narrow || !record_bytes || !rec_host || (mixed && !wz_host)) {
     set_error("stage_records: NULL output");
     return ODF_E_INVALID;
   }
@@ -892,11 +902,13 @@ odf_status odf_stage_records(odf_plan_t* p, const odf_request* r, int32_t point,
   Batch B;
   if ((st = stage_prefix(p, r, point, &B, mixed ? 0 : 1, nullptr)) != ODF_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(p->opts.stream);
-  int32_t ns = 0;
+  int32_t ns = 0, nn = 0;
   HIP_TRY(hipMemcpyAsync(&ns, B.nsurv, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&nn, B.nsurv_n, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const int64_t rb = mixed ? (int64_t)sizeof(Rec32) : (int64_t)sizeof(Rec64);
   *n_surv = ns;
+  *n_narrow = nn;
   *record_bytes = (int32_t)rb;
   if (ns > capacity) {
     set_error("stage_records: %d survivors, capacity %lld", ns, (long long)capacity);

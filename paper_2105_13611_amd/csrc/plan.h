@@ -24,8 +24,9 @@ void g_last_error_clear();
 
 // Layout of one batch slot inside the workspace.
 struct SlotLayout {
-  int64_t off_T, off_logP, off_vt, off_abund, off_state, off_pop, off_bT, off_flags, off_blk,
-      off_nsurv, off_hmax, off_nsamp, off_nit, off_rec, off_win, off_wz, off_kappa, off_gscr;
+  int64_t off_T, off_logP, off_vt, off_abund, off_state, off_pop, off_bT, off_flags, off_wline, off_blk,
+      off_nsurv, off_nsurv_n, off_hmax, off_hmax_w, off_nsamp, off_nit, off_rec, off_win, off_wz,
+      off_kappa, off_gscr;
   int64_t bytes;      // total bytes of the slot
   int32_t points;     // points per slot
 };

@@ -105,8 +105,8 @@ SIGNATURES = {
     "odf_debug_fail_next_batch": (C.c_int, [C.c_void_p, C.c_int64]),
     "odf_debug_set_newton_limit": (C.c_int, [C.c_void_p, C.c_int32]),
     "odf_stage_times": (C.c_int, [C.c_void_p, _D, _D, _I64, C.c_int32]),
-    "odf_stage_records": (C.c_int, [C.c_void_p, C.POINTER(OdfRequest), C.c_int32, _I64, _I32, C.c_void_p,
-                                    C.c_int64, _I32]),
+    "odf_stage_records": (C.c_int, [C.c_void_p, C.POINTER(OdfRequest), C.c_int32, _I64, _I64, _I32,
+                                    C.c_void_p, C.c_int64, _I32]),
     "odf_reduce_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "odf_noalloc_scratch_need": (C.c_int64, [C.c_void_p, C.c_int32]),
 }
@@ -379,18 +379,19 @@ class Plan:
 
     def stage_records(self, abundance, points, point=0):
         """Survivor records of one point as the plan's Voigt kernel reads
-        them: (structured array, (J, packed zones) int32 pairs or None)."""
+        them: (structured array, (J, packed zones) int32 pairs or None, the
+        number of narrow-class records, which come first)."""
         dt = self.REC32 if self.precision == "mixed" else self.REC64
         cap = max(self.n_lines, 1)
         rec = np.zeros(cap, dtype=dt)
         wz = np.zeros((cap, 2), dtype=np.int32)
-        ns, rb = C.c_int64(), C.c_int32()
+        ns, nn, rb = C.c_int64(), C.c_int64(), C.c_int32()
         r, keep = _request(abundance, points, 0)
-        _check(lib().odf_stage_records(self.handle, C.byref(r), int(point), C.byref(ns), C.byref(rb),
-                                       C.c_void_p(rec.ctypes.data), cap, _ptr(wz, _I32)))
+        _check(lib().odf_stage_records(self.handle, C.byref(r), int(point), C.byref(ns), C.byref(nn),
+                                       C.byref(rb), C.c_void_p(rec.ctypes.data), cap, _ptr(wz, _I32)))
         assert rb.value == dt.itemsize
         n = ns.value
-        return rec[:n].copy(), (wz[:n].copy() if self.precision == "mixed" else None)
+        return rec[:n].copy(), (wz[:n].copy() if self.precision == "mixed" else None), nn.value
 
     def stage_state(self, abundance, points, point=0):
         """Gas state of one point: dict(n_e, n_heavy, n_H, rho, iterations)."""

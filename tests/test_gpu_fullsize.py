@@ -142,7 +142,10 @@ def test_served_stream_against_oracle():
         pts = r.points.take(np.asarray(q["point_index"]))
         np.testing.assert_array_equal(pts.T_K, q["T_K"])
         np.testing.assert_array_equal(pts.log10_P, q["log10_P"])
-    with odf.plan_for(w, precision="mixed", workspace_bytes=WORKSPACE) as plan:
+    # a pool that holds three of these requests' footprints at once
+    with odf.plan_for(w, precision="mixed", workspace_bytes=WORKSPACE) as probe:
+        ws = 3 * probe.request_footprint(max(r.points.n_points for r in w.requests)) + (1 << 30)
+    with odf.plan_for(w, precision="mixed", workspace_bytes=ws) as plan:
         tickets = [plan.submit(r.abundance, r.points) for r in w.requests]
         stats = [plan.wait(t, 600.0) for t, _ in tickets]
         torch.cuda.synchronize()

@@ -66,7 +66,7 @@ def test_fp32_records_against_the_oracle(work):
     with odf.plan_for(w, precision="mixed", workspace_bytes=64 << 20) as plan:
         for p in range(w.points.n_points):
             print(f"[records] point {p}: T={w.points.T_K[p]} logP={w.points.log10_P[p]}", flush=True)
-            rec, wz = plan.stage_records(w.species.abundance, w.points, p)
+            rec, wz, n_narrow = plan.stage_records(w.species.abundance, w.points, p)
             sl = plan.stage_lines(w.species.abundance, w.points, p)
             torch.cuda.synchronize()
             lq = oracle.line_quantities(w.lines, w.species, w.species.abundance, float(w.points.T_K[p]),
@@ -74,6 +74,17 @@ def test_fp32_records_against_the_oracle(work):
                                         w.options)
             n = rec.size
             assert n == sl["n_surv"] and n > 100
+            # the kernel's order: half-windows of at most 1024 points first, then
+            # the others, each class in wavelength order (stage_lines gives
+            # wavelength order)
+            J = np.rint(lq["jstar"][sl["orig"]]).astype(np.int64)
+            half = np.maximum(J - sl["jlo"], sl["jhi"] - J) + 1
+            narrow = half <= 1024
+            assert n_narrow == int(narrow.sum())
+            order = np.concatenate([np.nonzero(narrow)[0], np.nonzero(~narrow)[0]])
+            sl = {k: (v[order] if isinstance(v, np.ndarray) else v) for k, v in sl.items()}
+            assert np.all(np.diff(w.lines.lambda_nm[sl["orig"][:n_narrow]]) >= 0)
+            assert np.all(np.diff(w.lines.lambda_nm[sl["orig"][n_narrow:]]) >= 0)
             o = sl["orig"]
             np.testing.assert_array_equal(rec["jlo"], sl["jlo"])
             np.testing.assert_array_equal(rec["jhi"], sl["jhi"])
