@@ -608,6 +608,7 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
     if (kRec64) {
       czh = e.a < kFarR64 ? zone_half(kFarR64, c1) : -1;
       z40 = e.a < kFar4R64 ? zone_half(kFar4R64, c1) : -1;
+      B.wz[slot] = make_int2(J, z40);
     } else {
       // no zone: -32768, which the Voigt kernel's row masks read as empty
       const int32_t far = e.a < kFarR32 ? min(zone_half(kFarR32, c1), 32767) : -32768;

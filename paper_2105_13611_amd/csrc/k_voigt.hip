@@ -697,6 +697,17 @@ __device__ __forceinline__ void line64(const Rec64& l, int t_lo, int t_hi, int l
   }
 }
 
+// A far-field record (FP64): its four-node fraction at this lane's node,
+// added to the node's sum in LDS.
+__device__ __forceinline__ void far_field64(const Rec64& l, int t_lo, int lane, double lnq,
+                                            const QuadConsts* __restrict__ Q,
+                                            double* __restrict__ lff) {
+  const Gh4Frac g4 = gh4_fraction(l.y, l.S, Q);
+  const double d = (double)(l.J - t_lo) + l.phi - Q->ff_off64[lane];
+  const double x = x_of_d64(d, l.c1, lnq);
+  lff[lane] += gh4_value(x * x, g4);
+}
+
 // A whole FP64 record with one scalar-memory wait (as load_rec32).
 __device__ __forceinline__ Rec64 load_rec64(const Rec64* __restrict__ p) {
   const int4* q = reinterpret_cast<const int4*>(p);
@@ -724,6 +735,7 @@ __device__ __forceinline__ Rec64 load_rec64(const Rec64* __restrict__ p) {
 __global__ __launch_bounds__(256, 4) void k_voigt64(Params P, Batch B, const QuadConsts* __restrict__ Q,
                                                  int tiles_per_point, int total) {
   __shared__ double lds_s[kWavesPerWG][kWavePoints];
+  __shared__ double lds_ff[kWavesPerWG][kWave];   // far-field node sums
   const int logical = tile_order(blockIdx.x, total);
   if (logical >= total) return;
   const int p = logical / tiles_per_point;
@@ -737,6 +749,9 @@ __global__ __launch_bounds__(256, 4) void k_voigt64(Params P, Batch B, const Qua
   if (t_lo >= N) return;
   const int t_hi = min(t_lo + kWavePoints - 1, N - 1);
   double* ls = lds_s[wid];
+  double* lff = lds_ff[wid];
+  lff[lane] = 0.0;
+  bool any_ff = false;
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) ls[rr * 64 + lane] = 0.0;
   double as[kRows];
@@ -744,6 +759,7 @@ __global__ __launch_bounds__(256, 4) void k_voigt64(Params P, Batch B, const Qua
   for (int rr = 0; rr < kRows; ++rr) as[rr] = 0.0;
   const Rec64* __restrict__ rec = reinterpret_cast<const Rec64*>(B.rec) + p * B.rec_stride;
   const int2* __restrict__ win = B.win + p * B.rec_stride;
+  const int2* __restrict__ wz = B.wz + p * B.rec_stride;
   const int ns = B.nsurv[p];
   const int nn = B.nsurv_n[p];
   const double lnq = P.lnq;
@@ -757,16 +773,41 @@ __global__ __launch_bounds__(256, 4) void k_voigt64(Params P, Batch B, const Qua
   const int c1w = nn + upper_bound_J(rec + nn, ns - nn, t_hi + Hw);
   const int n1 = c1n - c0n, nv = n1 + (c1w - c0w);
   const int shift = c0w - c0n - n1;
-  // windows one per lane (next 64 prefetched), records by scalar loads
+  // windows and (J, z40) one per lane (next 64 prefetched), records by
+  // scalar loads
   const int2 none = make_int2(0x7fffffff, -0x7fffffff - 1);
-  int2 nxt = none;
-  if (lane < nv) nxt = win[c0n + lane + (lane >= n1 ? shift : 0)];
+  int2 nxt = none, nxz = make_int2(0, -1);
+  if (lane < nv) {
+    const int r = c0n + lane + (lane >= n1 ? shift : 0);
+    nxt = win[r];
+    nxz = wz[r];
+  }
   for (int vb = 0; vb < nv; vb += 64) {
-    const int2 cur = nxt;
+    const int2 cur = nxt, cz = nxz;
     nxt = none;
     const int vn = vb + 64 + lane;
-    if (vn < nv) nxt = win[c0n + vn + (vn >= n1 ? shift : 0)];
+    if (vn < nv) {
+      const int r = c0n + vn + (vn >= n1 ? shift : 0);
+      nxt = win[r];
+      nxz = wz[r];
+    }
     unsigned long long m = __ballot(cur.x <= t_hi && cur.y >= t_lo);
+    if (!m) continue;
+    // far field: window over the tile, |x| < 40 zone outside it, centre more
+    // than kFFDist64 points away
+    const int rel = cz.x - t_lo;
+    const bool ff = cur.x <= t_lo && cur.y >= t_hi &&
+                    (cz.y < 0 || cz.x + cz.y < t_lo || cz.x - cz.y > t_hi) &&
+                    (rel < -kFFDist64 || rel > kWavePoints - 1 + kFFDist64);
+    unsigned long long mf = m & __ballot(ff);
+    m &= ~mf;
+    if (mf) any_ff = true;
+    while (mf) {
+      const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)mf) - 1);
+      mf &= mf - 1;
+      const int r = c0n + vb + k + (vb + k >= n1 ? shift : 0);
+      far_field64(load_rec64(rec + r), t_lo, lane, lnq, Q, lff);
+    }
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1);
       m &= m - 1;
@@ -778,7 +819,15 @@ __global__ __launch_bounds__(256, 4) void k_voigt64(Params P, Batch B, const Qua
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) {
     const int j = t_lo + rr * 64 + lane;
-    if (j <= t_hi) kap[j] = as[rr] + ls[rr * 64 + lane];
+    double w = 0.0;
+    if (any_ff) {
+      // point 64 (rr % 4) + lane of quarter rr / 4 from that quarter's nodes
+      const double* __restrict__ M = Q->ff_M64[64 * (rr & 3) + lane];
+      const double* __restrict__ f = lff + kFFNodes * (rr >> 2);
+#pragma unroll
+      for (int n = 0; n < kFFNodes; ++n) w = fma(M[n], f[n], w);
+    }
+    if (j <= t_hi) kap[j] = as[rr] + ls[rr * 64 + lane] + w;
   }
 }
 

@@ -84,6 +84,13 @@ constexpr int kSerIntervals = 128;
 constexpr int kFFNodes = 16;
 constexpr int kFFQuarter = 256;
 constexpr int kFFDist = 64;
+// FP64 far field: the same 64 nodes per tile for lines whose window covers
+// the tile, whose |x| < 40 zone misses it (so the four-node fraction holds
+// over the whole tile) and whose centre lies more than kFFDist64 points
+// outside it.  At that distance the float64 interpolation error stays below
+// 1e-12 of the line's part (damping 1e-4 to 1e5, Doppler widths of 1 to 60
+// points), under the four-node rule's own 3e-12.
+constexpr int kFFDist64 = 384;
 
 // Half-width in fine points of the zone where |x| < R may occur, for a line
 // with c1 = ln q / b: |x| >= R implies |d| >= R / (1.02 c1) (|d ln q| <= 0.031).
@@ -108,6 +115,11 @@ struct QuadConsts {
   float ff_w[kFFNodes];    // their barycentric weights (-1)^n sin((2n + 1) pi / 32)
   float ff_off[64];        // node of lane l, in points after the tile's first point:
                            // Chebyshev point l % 16 of quarter l / 16
+  double ff_off64[64];     // the same in FP64
+  // FP64 interpolation: the far field at point k of a quarter is
+  // sum_n ff_M64[k][n] f_n over its 16 node values f_n (barycentric weights
+  // of the Chebyshev points, normalised at each point)
+  double ff_M64[kFFQuarter][kFFNodes];
   // T_{2k+1} on interval i: c0 + c1 f + c2 f^2 + c3 f^3, f = s kSerIntervals - i
   alignas(16) float ser[kSerTerms][kSerIntervals][4];
 };
@@ -170,7 +182,7 @@ struct alignas(16) Rec32 {
 struct alignas(16) Rec64 {
   int32_t J, jlo, jhi;
   int32_t czh;      // half-width of the zone where |x| < 8 may occur (-1: none)
-  int32_t z40;      // the same for |x| < 40
+  int32_t z40;      // the same for |x| < 40 (the kernel reads it from the (J, z40) array)
   int32_t li;       // sorted line index (stage checks)
   int32_t pad0, pad1;
   double phi, S, y, c1;
@@ -197,7 +209,8 @@ struct Batch {
   int32_t* nit;         // [B]         ionisation-equilibrium steps (0: fixed P_e; < 0: not converged)
   void* rec;            // [B][L] Rec32 or Rec64
   int2* win;            // [B][L] (jlo, jhi) of each record, scanned by the Voigt kernels
-  int2* wz;             // [B][L] (J, czh) of each FP32 record, read with its window (mixed plans)
+  int2* wz;             // [B][L] (J, czh) of each FP32 record or (J, z40) of each FP64 one, read
+                        //        with its window
   void* kappa;          // [B][N] float or double
   int64_t rec_stride;   // = L
   int64_t kappa_stride; // = N

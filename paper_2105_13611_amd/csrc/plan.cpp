@@ -226,7 +226,7 @@ SlotLayout make_slot(const odf_plan_s* p, int32_t pts) {
   s.off_nit = take(4 * pts);
   s.off_rec = take((mixed ? (int64_t)sizeof(Rec32) : (int64_t)sizeof(Rec64)) * std::max<int64_t>(L, 1) * pts);
   s.off_win = take((int64_t)sizeof(int2) * std::max<int64_t>(L, 1) * pts);
-  s.off_wz = take(mixed ? (int64_t)sizeof(int2) * std::max<int64_t>(L, 1) * pts : 0);
+  s.off_wz = take((int64_t)sizeof(int2) * std::max<int64_t>(L, 1) * pts);
   s.off_kappa = take((mixed ? 4 : 8) * p->N * pts);
   s.off_gscr = take((mixed ? 4 : 8) * std::max<int64_t>(p->gscr_elems, 1) * pts);
   s.bytes = o;

@@ -174,6 +174,20 @@ QuadConsts make_quad_consts() {
     const long double th = (2 * (l % kFFNodes) + 1) * pi / (2 * kFFNodes);
     const long double half = 0.5L * (kFFQuarter - 1);
     Q.ff_off[l] = (float)(kFFQuarter * (l / kFFNodes) + half + half * std::cos(th));
+    Q.ff_off64[l] = (double)(kFFQuarter * (l / kFFNodes) + half + half * std::cos(th));
+  }
+  // barycentric weights w_n / (t - s_n), normalised, at the 256 points of a
+  // quarter (t in [-1, 1]; no point coincides with a node)
+  for (int k = 0; k < kFFQuarter; ++k) {
+    const long double half = 0.5L * (kFFQuarter - 1);
+    const long double t = ((long double)k - half) / half;
+    long double r[kFFNodes], sum = 0.0L;
+    for (int n = 0; n < kFFNodes; ++n) {
+      const long double th = (2 * n + 1) * pi / (2 * kFFNodes);
+      r[n] = (n % 2 ? -1.0L : 1.0L) * std::sin(th) / (t - std::cos(th));
+      sum += r[n];
+    }
+    for (int n = 0; n < kFFNodes; ++n) Q.ff_M64[k][n] = (double)(r[n] / sum);
   }
   series_table(Q);
   return Q;
