@@ -1,13 +1,16 @@
-"""Far field of the mixed Voigt sums.
+"""Far field of the Voigt sums, both precisions.
 
-A (line, tile) pair whose window covers the whole 1024-point tile, whose
-|x| < 15 zone misses it and whose centre lies more than 64 points outside it
-is evaluated at 64 nodes of the tile and interpolated.  Five strong, strongly
-damped lines (two centred outside the grid) with windows over the whole grid
-of config 1 put most (line, tile) pairs of every point in that regime, so the
-fine-grid opacity checks the interpolation against the oracle, which adds
-every sample.  Tolerances as in the other fine-grid tests: 2e-4 (mixed) and
-1e-10 (FP64, which adds every sample too) relative to max(kappa, floor).
+Mixed path: a (line, tile) pair whose window covers the whole 1024-point
+tile, whose |x| < 15 zone misses it and whose centre lies more than 64
+points outside it is evaluated at 64 nodes of the tile and interpolated.
+FP64 path: the same with the |x| < 40 zone and a centre more than 384 points
+outside the tile, the line's four-node fraction and an FP64 interpolation
+matrix.  Five strong, strongly damped lines (two centred outside the grid)
+with windows over the whole grid of config 1 put most (line, tile) pairs of
+every point in that regime, so the fine-grid opacity checks the
+interpolation against the oracle, which adds every sample.  Tolerances as in
+the other fine-grid tests: 2e-4 (mixed) and 1e-10 (FP64) relative to
+max(kappa, floor).
 """
 from dataclasses import replace
 
