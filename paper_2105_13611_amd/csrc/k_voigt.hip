@@ -10,9 +10,10 @@
 // windows with one ballot, broadcasts each intersecting record with readlane
 // and evaluates only the rows the window covers.  No atomics: each point is
 // summed by one lane in the survivors' wavelength order, so results are
-// bit-reproducible.  In FP32, a line whose part is smooth over the whole
-// tile (window over the tile, centre far outside it) is evaluated only at
-// 64 nodes of the tile, whose sums are interpolated at the end.
+// bit-reproducible.  A line whose part is smooth over the whole tile
+// (window over the tile, centre far outside it) is evaluated only at nodes
+// of the tile, whose sums are interpolated at the end; in FP32 the farther
+// such lines use fewer nodes, several lines to a 64-lane pass.
 //
 // Re w is evaluated in real arithmetic only, so that its relative accuracy
 // holds where Re w << |w| (far wings of weakly damped lines):
@@ -242,8 +243,9 @@ __device__ __forceinline__ void rows32(unsigned rows, float d0, float q64, const
 // compute values that nobody reads.  A zone half-width of -32768 gives no
 // rows.  A record whose window covers the tile, whose |x| < 15 zone misses
 // it and whose centre lies more than kFFDist points outside the tile's 1024
-// points is a far-field record: fm = nc = 0 (any other record that meets
-// the tile has a row in fm).
+// points is a far-field record: fm = nc = 0 and tier 1 to 4 by the centre's
+// distance (beyond kFFDist, kFFTier2, kFFTier3, kFFTier4); tier 0 for the
+// others.
 __device__ __forceinline__ unsigned zone_rows_v(int rel, int z) {
   const int lo = min(max((rel - z) >> 6, 0), kRows);
   const int hi = min(max((rel + z) >> 6, -1), kRows - 1);
@@ -251,7 +253,7 @@ __device__ __forceinline__ unsigned zone_rows_v(int rel, int z) {
 }
 
 __device__ __forceinline__ void row_masks(int2 w, int2 jz, int t_lo, int t_hi, unsigned& fm,
-                                          unsigned& nc) {
+                                          unsigned& nc, int& tier) {
   const int jl = max(w.x, t_lo) - t_lo;
   const int jh = min(w.y, t_hi) - t_lo;
   const int r_lo = (jl >> 6) & 31, r_hi = (jh >> 6) & 31;
@@ -262,11 +264,13 @@ __device__ __forceinline__ void row_masks(int2 w, int2 jz, int t_lo, int t_hi, u
   const unsigned core = zone_rows_v(rel, jz.y >> 16);
   fm = (rows & ~(near | edge)) | (((near | edge) & rows) << 16);
   nc = (near & rows) | (core << 16);
-  const bool far_field = w.x <= t_lo && w.y >= t_hi && near == 0u &&
-                         (rel < -kFFDist || rel > kWavePoints - 1 + kFFDist);
+  const int dist = max(-rel, rel - (kWavePoints - 1));
+  const bool far_field = w.x <= t_lo && w.y >= t_hi && near == 0u && dist > kFFDist;
+  tier = 0;
   if (far_field) {
     fm = 0u;
     nc = 0u;
+    tier = 1 + (dist > kFFTier2) + (dist > kFFTier3) + (dist > kFFTier4);
   }
 }
 
@@ -319,12 +323,10 @@ __device__ __forceinline__ void line32(const Rec32& l, unsigned far_masked, unsi
   }
 }
 
-// A far-field record at this lane's node, added with compensation to the
-// node's sum in LDS (kept out of registers: the row sums use them all).
-__device__ __forceinline__ void far_field32(const Rec32& l, int t_lo, int lane, float lnq2, float lnq6,
-                                            const QuadConsts* __restrict__ Q, float* __restrict__ lfs,
-                                            float* __restrict__ lfc) {
-  const float ffoff = Q->ff_off[lane];
+// A nearest-tier far-field record (broadcast in scalar registers) at this
+// lane's quarter node, at offset ffoff after the tile's first point.
+__device__ __forceinline__ float far_node32(const Rec32& l, int t_lo, float ffoff, float lnq2,
+                                            float lnq6) {
   Far32 f;
   f.c1 = l.c1;
   f.c2 = l.c1 * lnq2;
@@ -335,24 +337,103 @@ __device__ __forceinline__ void far_field32(const Rec32& l, int t_lo, int lane, 
   f.D = l.D;
   f.E = l.E;
   const float d = (float)(l.J - t_lo) + l.phi - ffoff;
-  const float v = far_value(x_of_d32(d, f), f);
-  float sum = lfs[lane], c = lfc[lane];
-  kahan_add(sum, c, v);
-  lfs[lane] = sum;
-  lfc[lane] = c;
+  return far_value(x_of_d32(d, f), f);
+}
+
+// The far-field records of one whole-tile tier among the current 64 (bit
+// mask mt, lane k holding record r_own), K nodes over the tile and 64 / K
+// records per pass: lane group g = lane / K takes the g-th record of the
+// pass at node lane % K (offset off).  The records' indices go through an
+// LDS queue in lane order; each lane then reads its record's fields with
+// vector loads.  Returns this lane's sum over the passes (at most 64 / (64
+// / K) = K terms, added plainly).
+template <int K>
+__device__ __forceinline__ float far_tier32(unsigned long long mt, int r_own, int lane, int t_lo,
+                                            float off, int* __restrict__ q,
+                                            const Rec32* __restrict__ rec, float lnq2, float lnq6) {
+  constexpr int kShift = K == 32 ? 5 : (K == 16 ? 4 : 3);
+  static_assert((1 << kShift) == K, "tiers of 32, 16 or 8 nodes");
+  if ((mt >> lane) & 1ull) {
+    const unsigned rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mt >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((unsigned)mt, 0u));
+    q[rank] = r_own;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const int cnt = __popcll(mt);
+  const int g = lane >> kShift;
+  float acc = 0.0f;
+  for (int p = 0; p < cnt; p += 64 / K) {
+    // lanes past the last record read the last one again and add nothing
+    const int qi = p + g;
+    const int r = q[min(qi, cnt - 1)];
+    const int* __restrict__ w = reinterpret_cast<const int*>(rec + r);
+    const int J = w[0];
+    const float4 a = *reinterpret_cast<const float4*>(w + 4);   // phi, c1, A, B
+    const float2 b = *reinterpret_cast<const float2*>(w + 8);   // D, E
+    Far32 f;
+    f.c1 = a.y;
+    f.c2 = a.y * lnq2;
+    f.c3 = a.y * lnq6;
+    f.step = 0.0f;
+    f.A = a.z;
+    f.B = a.w;
+    f.D = b.x;
+    f.E = b.y;
+    const float d = (float)(J - t_lo) + a.x - off;
+    const float v = far_value(x_of_d32(d, f), f);
+    acc += qi < cnt ? v : 0.0f;
+  }
+  __builtin_amdgcn_wave_barrier();
+  return acc;
+}
+
+// v, made opaque to the optimiser: a load indexed by it stays where it is
+// written instead of being hoisted out of the record loop, where its result
+// would hold a register through the line loop (which has none to spare).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Per-wave LDS: the row sums' compensations, the far-field sums and the
+// record queue.
+struct WaveLds32 {
+  // Kahan compensations of the 16 row sums, two to a word as the upper 16
+  // bits of the FP32 value (8 significant bits): a compensation is at most
+  // about an ulp of its sum, so truncating it loses at most 2^-8 ulp per
+  // flush
+  unsigned rc[kRows / 2][kWave];
+  // far-field sums and their compensations: [0] the quarter nodes (lane l
+  // at node l % 16 of quarter l / 16), [1..3] the lane slots of the 32-,
+  // 16- and 8-node tiers (lane l at node l % K of lane group l / K)
+  float fs[4][kWave];
+  float fc[4][kWave];
+  // one tier's record queue; at the end the whole-tile tiers' node values
+  int q[kWave];
+};
+
+__device__ __forceinline__ void kahan_lds(float* __restrict__ s, float* __restrict__ c, int lane,
+                                          float v) {
+  float sum = s[lane], cc = c[lane];
+  kahan_add(sum, cc, v);
+  s[lane] = sum;
+  c[lane] = cc;
 }
 
 // Compensated (Kahan) addition of the partial sums into the row sums: the
-// running sums s stay in registers, their compensations c in LDS.
-__device__ __forceinline__ void flush32(float (&s)[kRows], RowVec& p, float* __restrict__ lc,
+// running sums s stay in registers, their compensations in LDS.
+__device__ __forceinline__ void flush32(float (&s)[kRows], RowVec& p, unsigned* __restrict__ rc,
                                         int lane) {
 #pragma unroll
-  for (int rr = 0; rr < kRows; ++rr) {
-    const int o = rr * 64 + lane;
-    float c = lc[o];
-    kahan_add(s[rr], c, p[rr]);
-    lc[o] = c;
-    p[rr] = 0.0f;
+  for (int i = 0; i < kRows / 2; ++i) {
+    const int o = i * 64 + lane;
+    const unsigned w = rc[o];
+    float c0 = __uint_as_float(w << 16), c1 = __uint_as_float(w & 0xffff0000u);
+    kahan_add(s[2 * i], c0, p[2 * i]);
+    kahan_add(s[2 * i + 1], c1, p[2 * i + 1]);
+    rc[o] = (__float_as_uint(c0) >> 16) | (__float_as_uint(c1) & 0xffff0000u);
+    p[2 * i] = 0.0f;
+    p[2 * i + 1] = 0.0f;
   }
 }
 
@@ -413,15 +494,15 @@ constexpr int kFlushLines = 64;
 __global__ __launch_bounds__(256, 6) void k_voigt32(Params P, Batch B,
                                                     const QuadConsts* __restrict__ Q,
                                                     int tiles_per_point, int total) {
-  // per wave: the Kahan compensations of the row sums, then the far-field
-  // node sums and their compensations (one base address for all three)
-  __shared__ float lds_c[kWavesPerWG][kWavePoints + 2 * kWave];
+  __shared__ WaveLds32 lds_w[kWavesPerWG];
   __shared__ float4 lds_ser[kSerTerms * kSerIntervals]; // small-damping series table
+  __shared__ float lds_toff[kFFTileNodes];               // whole-tile tier node positions
   const int logical = tile_order(blockIdx.x, total);
   if (logical >= total) return;
   {
     const float4* __restrict__ src = reinterpret_cast<const float4*>(&Q->ser[0][0][0]);
     for (int i = threadIdx.x; i < kSerTerms * kSerIntervals; i += blockDim.x) lds_ser[i] = src[i];
+    if (threadIdx.x < kFFTileNodes) lds_toff[threadIdx.x] = Q->ff_toff[threadIdx.x];
     __syncthreads();
   }
   const int pt = logical / tiles_per_point;
@@ -434,20 +515,22 @@ __global__ __launch_bounds__(256, 6) void k_voigt32(Params P, Batch B,
   const int t_lo = tile * kWGPoints + wid * kWavePoints;
   if (t_lo >= N) return;
   const int t_hi = min(t_lo + kWavePoints - 1, N - 1);
-  float* lc = lds_c[wid];
-  float* lfs = lc + kWavePoints;
-  float* lfc = lfs + kWave;
-  lfs[lane] = 0.0f;
-  lfc[lane] = 0.0f;
-  bool any_ff = false;
+  WaveLds32& L = lds_w[wid];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    L.fs[k][lane] = 0.0f;
+    L.fc[k][lane] = 0.0f;
+  }
+  unsigned ffmask = 0u;   // far-field tiers seen (bit t - 1 for tier t)
   float s[kRows];
   RowVec p;
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) {
-    lc[rr * 64 + lane] = 0.0f;
     s[rr] = 0.0f;
     p[rr] = 0.0f;
   }
+#pragma unroll
+  for (int i = 0; i < kRows / 2; ++i) L.rc[i][lane] = 0u;
   const Rec32* __restrict__ rec = reinterpret_cast<const Rec32*>(B.rec) + pt * B.rec_stride;
   const int2* __restrict__ win = B.win + pt * B.rec_stride;
   const int2* __restrict__ wz = B.wz + pt * B.rec_stride;
@@ -491,17 +574,46 @@ __global__ __launch_bounds__(256, 6) void k_voigt32(Params P, Batch B,
     unsigned long long m = __ballot(cur.x <= t_hi && cur.y >= t_lo);
     if (!m) continue;
     unsigned fm, nc;
-    row_masks(cur, cz, t_lo, t_hi, fm, nc);
-    // far-field records in a loop of their own (a branch between the two
-    // kinds inside one loop costs the row sums' registers spills)
-    unsigned long long mf = m & __ballot(fm == 0u);
-    m &= ~mf;
-    if (mf) any_ff = true;
-    while (mf) {
-      const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(mf));
-      mf &= mf - 1;
-      const int r = c0n + vb + k + (vb + k >= n1 ? shift : 0);
-      far_field32(load_rec32(rec + r), t_lo, lane, lnq2, lnq6, Q, lfs, lfc);
+    int tier;
+    row_masks(cur, cz, t_lo, t_hi, fm, nc, tier);
+    // far-field records in loops of their own (a branch between the two
+    // kinds inside one loop costs the row sums' registers spills): the
+    // nearest tier one record at a time at the quarter nodes, the others
+    // several to a pass
+    unsigned long long mf = m & __ballot(tier == 1);
+    const unsigned long long m2 = m & __ballot(tier == 2);
+    const unsigned long long m3 = m & __ballot(tier == 3);
+    const unsigned long long m4 = m & __ballot(tier == 4);
+    m &= ~(mf | m2 | m3 | m4);
+    if (mf) {
+      ffmask |= 1u;
+      const float ffoff = Q->ff_off[opaque(lane)];
+      float acc = 0.0f;
+      while (mf) {
+        const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(mf));
+        mf &= mf - 1;
+        const int r = c0n + vb + k + (vb + k >= n1 ? shift : 0);
+        acc += far_node32(load_rec32(rec + r), t_lo, ffoff, lnq2, lnq6);
+      }
+      kahan_lds(L.fs[0], L.fc[0], lane, acc);
+    }
+    if (m2 | m3 | m4) {
+      const int r_own = c0n + vb + lane + (vb + lane >= n1 ? shift : 0);
+      if (m2) {
+        ffmask |= 2u;
+        kahan_lds(L.fs[1], L.fc[1], lane,
+                  far_tier32<32>(m2, r_own, lane, t_lo, lds_toff[opaque(lane) & 31], L.q, rec, lnq2, lnq6));
+      }
+      if (m3) {
+        ffmask |= 4u;
+        kahan_lds(L.fs[2], L.fc[2], lane,
+                  far_tier32<16>(m3, r_own, lane, t_lo, lds_toff[32 + (opaque(lane) & 15)], L.q, rec, lnq2, lnq6));
+      }
+      if (m4) {
+        ffmask |= 8u;
+        kahan_lds(L.fs[3], L.fc[3], lane,
+                  far_tier32<8>(m4, r_own, lane, t_lo, lds_toff[48 + (opaque(lane) & 7)], L.q, rec, lnq2, lnq6));
+      }
     }
     while (m) {
       const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(m));
@@ -510,20 +622,49 @@ __global__ __launch_bounds__(256, 6) void k_voigt32(Params P, Batch B,
       line32(load_rec32(rec + r), __builtin_amdgcn_readlane(fm, k),
              __builtin_amdgcn_readlane(nc, k), t_lo, lane, lnq2, lnq6, q64, g64, Q, lds_ser, p);
       if (++since_flush == kFlushLines) {
-        flush32(s, p, lc, lane);
+        flush32(s, p, &L.rc[0][0], lane);
         since_flush = 0;
       }
     }
   }
-  flush32(s, p, lc, lane);
-  if (any_ff) lfs[lane] -= lfc[lane];   // node values, read by every lane below
+  flush32(s, p, &L.rc[0][0], lane);
+  // the far field at this lane's quarter node: the nearest tier's sum plus
+  // each whole-tile tier's interpolant there; node values read by every lane
+  // below
+  if (ffmask) {
+    float ff = L.fs[0][lane] - L.fc[0][lane];
+    if (ffmask & 14u) {
+      // node n of a tier with K nodes: the sum of its 64 / K lane slots
+      float f = 0.0f;
+      if (lane < 32) {
+#pragma unroll
+        for (int g = 0; g < 2; ++g) f += L.fs[1][32 * g + lane] - L.fc[1][32 * g + lane];
+      } else if (lane < 48) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) f += L.fs[2][16 * g + lane - 32] - L.fc[2][16 * g + lane - 32];
+      } else if (lane < kFFTileNodes) {
+#pragma unroll
+        for (int g = 0; g < 8; ++g) f += L.fs[3][8 * g + lane - 48] - L.fc[3][8 * g + lane - 48];
+      }
+      float* nodes = reinterpret_cast<float*>(L.q);
+      nodes[lane] = f;
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll 8
+      for (int n = 0; n < kFFTileNodes; ++n) ff = fmaf(Q->ff_V[n][lane], nodes[n], ff);
+      __builtin_amdgcn_wave_barrier();
+    }
+    L.fs[0][lane] = ff;
+    __builtin_amdgcn_wave_barrier();
+  }
   float* kap = reinterpret_cast<float*>(B.kappa) + pt * B.kappa_stride;
 #pragma unroll
   for (int rr = 0; rr < kRows; ++rr) {
     const int j = t_lo + rr * 64 + lane;
-    const float v = s[rr] - lc[rr * 64 + lane];
-    const float w = any_ff ? far_field_at(lfs + kFFNodes * (rr >> 2), 64 * (rr & 3) + lane, Q) : 0.0f;
-    if (j <= t_hi) kap[j] = v + w;
+    const unsigned w = L.rc[rr >> 1][lane];
+    const float c = __uint_as_float((rr & 1) ? (w & 0xffff0000u) : (w << 16));
+    const float v = s[rr] - c;
+    const float ffv = ffmask ? far_field_at(L.fs[0] + kFFNodes * (rr >> 2), 64 * (rr & 3) + lane, Q) : 0.0f;
+    if (j <= t_hi) kap[j] = v + ffv;
   }
 }
 

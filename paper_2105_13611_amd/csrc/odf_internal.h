@@ -84,6 +84,20 @@ constexpr int kSerIntervals = 128;
 constexpr int kFFNodes = 16;
 constexpr int kFFQuarter = 256;
 constexpr int kFFDist = 64;
+// Distance tiers of the FP32 far field.  Farther lines are smoother over the
+// tile, and Chebyshev interpolation over the whole 1024-point tile converges
+// much faster per node than over a quarter, so lines whose centre lies more
+// than kFFTier2 (kFFTier3, kFFTier4) points outside the tile are evaluated
+// at only 32 (16, 8) Chebyshev points of the whole tile, which lets one
+// 64-lane pass take 2 (4, 8) lines.  At the end of the tile each tier's
+// interpolant is evaluated at the 64 quarter nodes (a fixed matrix of
+// Lagrange basis values) and added to their sums.  In FP32 arithmetic the
+// whole chain stays within 2.5e-6 of a line's part at each tier's edge
+// (damping 1e-4 to 1e5, Doppler widths of 1 to 100 points).
+constexpr int kFFTier2 = 128;
+constexpr int kFFTier3 = 384;
+constexpr int kFFTier4 = 1536;
+constexpr int kFFTileNodes = 32 + 16 + 8;   // nodes of the three whole-tile tiers, in that order
 // FP64 far field: the same 64 nodes per tile for lines whose window covers
 // the tile, whose |x| < 40 zone misses it (so the four-node fraction holds
 // over the whole tile) and whose centre lies more than kFFDist64 points
@@ -116,6 +130,12 @@ struct QuadConsts {
   float ff_off[64];        // node of lane l, in points after the tile's first point:
                            // Chebyshev point l % 16 of quarter l / 16
   double ff_off64[64];     // the same in FP64
+  // whole-tile tiers: node positions (points after the tile's first point)
+  // of the 32-, 16- and 8-point Chebyshev sets of the tile, one set after
+  // the other, and the Lagrange basis value of each node at each quarter
+  // node (ff_V[n][l]: node n at the node of lane l)
+  float ff_toff[kFFTileNodes];
+  float ff_V[kFFTileNodes][64];
   // FP64 interpolation: the far field at point k of a quarter is
   // sum_n ff_M64[k][n] f_n over its 16 node values f_n (barycentric weights
   // of the Chebyshev points, normalised at each point)

@@ -176,6 +176,32 @@ QuadConsts make_quad_consts() {
     Q.ff_off[l] = (float)(kFFQuarter * (l / kFFNodes) + half + half * std::cos(th));
     Q.ff_off64[l] = (double)(kFFQuarter * (l / kFFNodes) + half + half * std::cos(th));
   }
+  // whole-tile tiers: Chebyshev points of the first kind over the tile's
+  // 1024 points, and the Lagrange basis values at the quarter nodes from the
+  // barycentric formula, normalised (no quarter node coincides with a tile
+  // node: the closest pair is 0.002 points apart)
+  {
+    const long double half_t = 0.5L * (kWavePoints - 1);
+    const long double half_q = 0.5L * (kFFQuarter - 1);
+    int base = 0;
+    for (int K = 32; K >= 8; K /= 2) {
+      for (int n = 0; n < K; ++n)
+        Q.ff_toff[base + n] = (float)(half_t + half_t * std::cos((2 * n + 1) * pi / (2 * K)));
+      for (int l = 0; l < 64; ++l) {
+        const long double th_q = (2 * (l % kFFNodes) + 1) * pi / (2 * kFFNodes);
+        const long double xq = kFFQuarter * (l / kFFNodes) + half_q + half_q * std::cos(th_q);
+        const long double t = (xq - half_t) / half_t;
+        long double r[32], sum = 0.0L;
+        for (int n = 0; n < K; ++n) {
+          const long double th = (2 * n + 1) * pi / (2 * K);
+          r[n] = (n % 2 ? -1.0L : 1.0L) * std::sin(th) / (t - std::cos(th));
+          sum += r[n];
+        }
+        for (int n = 0; n < K; ++n) Q.ff_V[base + n][l] = (float)(r[n] / sum);
+      }
+      base += K;
+    }
+  }
   // barycentric weights w_n / (t - s_n), normalised, at the 256 points of a
   // quarter (t in [-1, 1]; no point coincides with a node)
   for (int k = 0; k < kFFQuarter; ++k) {
