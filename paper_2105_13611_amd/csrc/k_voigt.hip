@@ -818,7 +818,7 @@ __device__ __forceinline__ void line64(const Rec64& l, int t_lo, int t_hi, int l
     double v = (mid >> rr) & 1u ? l.S * gh8(x2, l.y, x2 + y2, Q) : gh4_value(x2, g4);
     const int rs = t_lo + 64 * rr;
     if (rs < l.jlo || rs + 63 > l.jhi) {
-      const int j = rs + lane;
+      const int j = rs + opaque(lane);   // recomputed, not kept (and spilled) for all 16 rows
       v = (j >= l.jlo && j <= l.jhi) ? v : 0.0;
     }
     as[rr] += v;
