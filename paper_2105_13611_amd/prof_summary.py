@@ -11,6 +11,8 @@
   python -m paper_2105_13611_amd.prof_summary flops --csv <counter csv>
       --bench-log <the profiled run's output> --kernel k_voigt32
       --command "<profiled command>" --out profiles/<name>.md
+  python -m paper_2105_13611_amd.prof_summary issue --csv <counter csv>
+      --kernel k_voigt32 --command "<profiled command>" --out profiles/<name>.md
 
 `traffic` scales each kernel's FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
 by the ratio of the bytes a plain elementwise copy of known size moves to what
@@ -182,6 +184,63 @@ def flops(args):
     open(args.out, "w").write("\n".join(lines) + "\n")
 
 
+# MI355X: 8 XCDs of 32 compute units, 4 SIMDs per compute unit
+XCDS = 8
+SIMDS = 256 * 4
+
+
+def issue(args):
+    """How busy the SIMDs' vector issue is over one kernel's dispatches.
+
+    GRBM_GUI_ACTIVE counts the cycles the GPU is busy, once per XCD, so over
+    a dispatch it sums to 8 x the dispatch's cycles; each SIMD then has that
+    many cycles / 8 to issue in.  A wave64 VALU instruction occupies its
+    SIMD for at least 4 cycles (16 lanes per cycle), so
+        VALU busy >= 4 SQ_INSTS_VALU / (SIMDs x GRBM_GUI_ACTIVE / 8)
+    (a lower bound: transcendental and FP64 instructions take longer)."""
+    counters = defaultdict(float)
+    launches = set()
+    for r in csv.DictReader(open(args.csv)):
+        if args.kernel in r["Kernel_Name"]:
+            counters[r["Counter_Name"]] += float(r["Counter_Value"])
+            launches.add(r["Dispatch_Id"])
+    g = counters.get("GRBM_GUI_ACTIVE", 0.0)
+    simd_cycles = SIMDS * g / XCDS
+    lines = [f"# Issue counters of {args.kernel}: {args.title}", "",
+             "Command (run from the repository root on one MI355X; one pass):", "",
+             "```", args.command, "```", "",
+             f"Sums over the {len(launches)} {args.kernel} dispatches of the run:", "",
+             "| counter | sum |", "|---|---|"]
+    for k in sorted(counters):
+        lines.append(f"| {k} | {counters[k]:.4e} |")
+    summary = dict(kernel=args.kernel, source_sha256=kernel_sources_sha256(), launches=len(launches))
+    lines.append("")
+    if g > 0 and "SQ_INSTS_VALU" in counters:
+        busy = 4.0 * counters["SQ_INSTS_VALU"] / simd_cycles
+        summary["valu_issue_busy_lower_bound"] = busy
+        lines.append(f"- GPU busy {g / XCDS:.4e} cycles (GRBM_GUI_ACTIVE / {XCDS} XCDs); each of the "
+                     f"{SIMDS} SIMDs issues VALU instructions in at least {100 * busy:.1f} % of them "
+                     "(4 cycles per wave64 VALU instruction)")
+        if "SQ_INSTS_VALU_TRANS_F32" in counters:
+            t = counters["SQ_INSTS_VALU_TRANS_F32"] / counters["SQ_INSTS_VALU"]
+            summary["trans_fraction"] = t
+            lines.append(f"- {100 * t:.1f} % of the VALU instructions are transcendental (FP32)")
+    if "SQ_WAVE_CYCLES" in counters:
+        w = counters["SQ_WAVE_CYCLES"]
+        for k, what in (("SQ_ACTIVE_INST_VALU", "issues VALU"), ("SQ_ACTIVE_INST_SCA", "issues scalar"),
+                        ("SQ_WAIT_INST_ANY", "waits on a dependency or memory")):
+            if k in counters:
+                lines.append(f"- a wave {what} in {100 * counters[k] / w:.1f} % of its cycles")
+    if "SQ_INSTS_SALU" in counters and "SQ_INSTS_VALU" in counters:
+        lines.append(f"- {counters['SQ_INSTS_SALU'] / counters['SQ_INSTS_VALU']:.2f} scalar instructions "
+                     "per VALU instruction")
+    if "SQ_INSTS_LDS" in counters and "SQ_INSTS_VALU" in counters:
+        lines.append(f"- {counters['SQ_INSTS_LDS'] / counters['SQ_INSTS_VALU']:.3f} LDS instructions "
+                     "per VALU instruction")
+    lines += ["", "```json", json.dumps(summary, indent=1), "```"]
+    open(args.out, "w").write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -214,8 +273,14 @@ def main():
     c.add_argument("--command", required=True)
     c.add_argument("--title", default="")
     c.add_argument("--out", required=True)
+    i = sub.add_parser("issue")
+    i.add_argument("--csv", required=True)
+    i.add_argument("--kernel", required=True)
+    i.add_argument("--command", required=True)
+    i.add_argument("--title", default="")
+    i.add_argument("--out", required=True)
     args = ap.parse_args()
-    {"stats": stats, "traffic": traffic, "passes": passes, "flops": flops}[args.cmd](args)
+    {"stats": stats, "traffic": traffic, "passes": passes, "flops": flops, "issue": issue}[args.cmd](args)
 
 
 if __name__ == "__main__":
