@@ -92,11 +92,15 @@ def stratified_points(points, n, seed=2):
     return np.array(sorted(set(idx[:n])), dtype=np.int64)
 
 
-def run_gpu(w, precision, steps, warmup, workspace_gb, points_idx=None, batch_points=0, sample=None):
+def run_gpu(w, precision, steps, warmup, workspace_gb, points_idx=None, batch_points=0, sample=None,
+            alone=True):
     """One leg: plan, `warmup` untimed steps, `steps` timed steps over the
     table (or its stratified subset).  sample = (point indices into
     w.points, bins): the output at those pairs is returned for the parity
-    block (points outside this leg's subset are left out)."""
+    block (points outside this leg's subset are left out).  alone: also time
+    the Voigt kernel by itself on 72 stratified points (after the timed
+    steps; a profiled run leaves it out so that its counters cover the
+    table's launches only)."""
     import numpy as np
     import torch
     from paper_2105_13611_amd import odf
@@ -130,7 +134,8 @@ def run_gpu(w, precision, steps, warmup, workspace_gb, points_idx=None, batch_po
             if int(i) in row:
                 got[int(i)] = out[row[int(i)]][list(sample[1])].double().cpu().numpy()
         res["sample_out"] = got
-    res["kernel_alone"] = kernel_alone(plan, w)
+    if alone:
+        res["kernel_alone"] = kernel_alone(plan, w)
     plan.destroy()
     del out
     torch.cuda.empty_cache()
@@ -233,8 +238,9 @@ def roofline(res, flop_per_sample, precision):
                                              "FP32 rate without packed FP32 instructions")
         out["note"] = ("achieved counts every Voigt sample of the method (each (line, fine point) pair in "
                        "the windows) at the far-wing cost; lines whose window covers a 1024-point tile from "
-                       "more than 64 points away are evaluated at 64 nodes of the tile and interpolated, so "
-                       "the kernel evaluates fewer samples: executed is what its VALU did (counters)")
+                       "more than 64 (128, 384, 1536) points away are evaluated at 64 (32, 16, 8) nodes of "
+                       "the tile and interpolated, so the kernel evaluates fewer samples: executed is what "
+                       "its VALU did (counters)")
     e = executed_flop_per_sample(precision)
     if e is not None:
         xa = samples * e / (ms / 1e3) / 1e12
@@ -726,6 +732,8 @@ def main():
     ap.add_argument("--workspace-gb", type=float, default=80.0)
     ap.add_argument("--batch-points", type=int, default=0, help="points per device batch (0 = automatic)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-kernel-alone", action="store_true",
+                    help="skip the Voigt-alone timing (profiled runs: counters then cover the table only)")
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--config", type=int, choices=sorted(WORKLOADS), default=2,
                     help="2: the 1425-point table (default); 3: the same at five vturb (7125 points); "
@@ -794,7 +802,8 @@ def run_table(args):
     for p in precs:
         steps, warmup = ((args.steps, args.warmup) if p == precs[0] or p == "mixed"
                          else (args.fp64_steps, args.fp64_warmup))
-        res[p] = run_gpu(w, p, steps, warmup, args.workspace_gb, idx, args.batch_points, sample)
+        res[p] = run_gpu(w, p, steps, warmup, args.workspace_gb, idx, args.batch_points, sample,
+                         alone=not args.no_kernel_alone)
         r = res[p]
         log(f"[bench] {p}: {r['n_points'] * r['steps'] / r['seconds']:.2f} points/s, "
             f"stage ms {r['stage_ms']}, plan {r['plan_seconds']:.1f} s")
