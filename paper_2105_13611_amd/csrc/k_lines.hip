@@ -307,7 +307,9 @@ __global__ void k_point_state(Params P, Batch B) {
           B.abundance[s] * n_H * f / (P.part_fn[s * K + k] * rho);
     }
     const double m = P.mass_amu[s] * kAmu;
-    B.bT[(int64_t)p * S + s] = sqrt(2.0 * kT / m + vt * vt) / kC;
+    const double bb = sqrt(2.0 * kT / m + vt * vt) / kC;
+    B.bT[((int64_t)p * S + s) * 2] = bb;              // b = dnu_D / nu_0
+    B.bT[((int64_t)p * S + s) * 2 + 1] = 1.0 / bb;    // and 1 / b, so lines multiply
   }
 }
 
@@ -373,18 +375,40 @@ __device__ __forceinline__ bool keep_line(double S, double a, double thr) {
   return S * erfcx(a) >= thr;
 }
 
+// The keep test in FP32 first: r = S / thr and a rounded to FP32 (within
+// 3 and 1 ulp), and the erfcx bounds above evaluated in FP32 (within about
+// 8 ulp, 5e-7), decide every line whose r erfcx(a) is more than 1e-5 away
+// from 1 the same way as the FP64 test.  1: keep, 0: drop, -1: too close,
+// take the FP64 test.
+__device__ __forceinline__ int keep_line32(float rf, float af) {
+  constexpr float kSqrtPiF = 1.77245385f;
+  if (!(rf < 1e30f)) return -1;
+  const float lo = 2.0f / (kSqrtPiF * (af + sqrtf(fmaf(af, af, 2.0f))));
+  if (rf * lo >= 1.0f + 1e-5f) return 1;
+  const float hi = 2.0f / (kSqrtPiF * (af + sqrtf(fmaf(af, af, (float)(4.0 / kPi)))));
+  if (rf * hi < 1.0f - 1e-5f) return 0;
+  return -1;
+}
+
+// The FP64 keep test out of line: it is taken only where the FP32 test
+// above leaves the decision open, and inlined it would hold registers that
+// the common path needs.
+__device__ __attribute__((noinline)) bool keep_line64(double S, double a, double thr) {
+  return keep_line(S, a, thr);
+}
+
 // Strength, damping, selection and window of one line at one point.  The
 // keep test is skipped when the caller already knows the line is kept
 // (kKept); kWindow false leaves the window out (the emission reads the one
-// the selection stored).
+// the selection stored).  bT holds (b, 1/b) per species of the point.
 template <bool kKept = false, bool kWindow = true>
 __device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d,
                                               const PointState& ps, const TFactors& tf,
                                               const double* __restrict__ pop,
                                               const double* __restrict__ bT) {
   LineEval e;
-  const double b = bT[d.sp];
-  const double S = d.amp * pop[d.ss] * tf.boltz * tf.stim / b;
+  const double b = bT[2 * d.sp], ib = bT[2 * d.sp + 1];
+  const double S = d.amp * pop[d.ss] * tf.boltz * tf.stim * ib;
   const double thr = d.thr;
   e.S = S;
   e.b = b;
@@ -393,12 +417,16 @@ __device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d
   e.jlo = 0;
   e.jhi = -1;
   if (!kKept && !(S >= thr)) return e;
-  const double a = (d.g_rad + d.g_stark * ps.cS + d.g_vdw * ps.cW) / b;
+  const double a = (d.g_rad + d.g_stark * ps.cS + d.g_vdw * ps.cW) * ib;
   e.a = a;
-  if (!kKept && !keep_line(S, a, thr)) return e;
   if (!kWindow) {
+    if (!kKept && !keep_line(S, a, thr)) return e;
     e.surv = true;
     return e;
+  }
+  if (!kKept) {
+    const int k32 = keep_line32((float)S / (float)thr, (float)a);
+    if (k32 == 0 || (k32 < 0 && !keep_line64(S, a, thr))) return e;
   }
   const double xg = sqrt(fmax(0.0, log(2.0 * S / thr)));
   const double xl = sqrt(2.0 * S * a / (kSqrtPi * thr));
@@ -442,7 +470,7 @@ __global__ __launch_bounds__(kLineBlock) void k_select(Params P, DevLines L, Bat
     if (valid) {
       tf.update(d, ps.T);
       const LineEval e = eval_line(P, d, ps, tf, B.pop + (int64_t)p * P.n_species * P.n_stages,
-                                   B.bT + (int64_t)p * P.n_species);
+                                   B.bT + (int64_t)p * 2 * P.n_species);
       s = e.surv;
       if (s) {
         half = max(J - e.jlo, e.jhi - J) + 1;
@@ -595,7 +623,7 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
     const PointState ps = B.state[p];
     tf.update(d, ps.T);
     LineEval e = eval_line<true, false>(P, d, ps, tf, B.pop + (int64_t)p * P.n_species * P.n_stages,
-                                        B.bT + (int64_t)p * P.n_species);
+                                        B.bT + (int64_t)p * 2 * P.n_species);
     const int2 wl = B.wline[(int64_t)p * B.rec_stride + i];
     e.jlo = wl.x;
     e.jhi = wl.y;

@@ -217,7 +217,7 @@ struct Batch {
   const double* abundance;  // [S]
   PointState* state;    // [B]
   double* pop;          // [B][S*K]
-  double* bT;           // [B][S]
+  double* bT;           // [B][S][2]: b and 1/b
   uint8_t* flags;       // [B][L]       0: dropped, 1: narrow survivor, 2: wide survivor
   int2* wline;          // [B][L]       survivors' windows (j_lo, j_hi) by line, from the selection
   int32_t* blk;         // [B][2][nblk] counts per class, then offsets within the class

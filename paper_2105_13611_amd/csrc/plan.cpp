@@ -214,7 +214,7 @@ SlotLayout make_slot(const odf_plan_s* p, int32_t pts) {
   s.off_abund = take(8 * S);
   s.off_state = take((int64_t)sizeof(PointState) * pts);
   s.off_pop = take(8 * S * K * pts);
-  s.off_bT = take(8 * S * pts);
+  s.off_bT = take(16 * S * pts);   // (b, 1/b) per species
   s.off_flags = take(std::max<int64_t>(L, 1) * pts);
   s.off_wline = take((int64_t)sizeof(int2) * std::max<int64_t>(L, 1) * pts);
   s.off_blk = take(4 * 2 * std::max<int64_t>(nblk, 1) * pts);

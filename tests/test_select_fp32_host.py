@@ -1,0 +1,55 @@
+"""The selection's FP32 keep test, checked on the host (no GPU).
+
+The selection kernel decides the keep test S erfcx(a) >= thr in FP32 first:
+the classical erfcx bounds evaluated in FP32 settle every line whose
+S erfcx(a) / thr is more than 1e-5 away from 1, and the FP64 test takes the
+rest.  This test runs the same FP32 operations in numpy float32 (one
+rounding per operation) on lines spread around the keep boundary (damping
+1e-5 to 1e5, half of them within 1e-3 of it): wherever the FP32 test
+decides, its decision must equal the exact one (scipy's erfcx, Sec. 2.1 and
+App. E); and it must decide for most lines, or it would not pay.
+"""
+import math
+
+import numpy as np
+from scipy.special import erfcx
+
+F = np.float32
+
+
+def fmaf(a, b, c):
+    return F(np.float64(a) * np.float64(b) + np.float64(c))
+
+
+def keep32(rf, af):
+    """keep_line32: 1 keep, 0 drop, -1 undecided."""
+    rf, af = F(rf), F(af)
+    if not rf < F(1e30):
+        return -1
+    sp = F(1.77245385)
+    lo = F(2.0) / (sp * (af + np.sqrt(fmaf(af, af, 2.0))))
+    if rf * lo >= F(1.0) + F(1e-5):
+        return 1
+    hi = F(2.0) / (sp * (af + np.sqrt(fmaf(af, af, F(4.0 / math.pi)))))
+    if rf * hi < F(1.0) - F(1e-5):
+        return 0
+    return -1
+
+
+def test_keep_decisions_equal_fp64():
+    rng = np.random.default_rng(12)
+    n = 200_000
+    a = 10.0 ** rng.uniform(-5, 5, n)
+    # ratios r erfcx(a) spread around 1, many within 1e-3 of it
+    q = np.where(rng.random(n) < 0.5, 10.0 ** rng.uniform(-3, 3, n), 1.0 + rng.uniform(-1e-3, 1e-3, n))
+    thr = 10.0 ** rng.uniform(-8, 2, n)
+    S = q / erfcx(a) * thr
+    decided = 0
+    for k in range(n):
+        d = keep32(F(S[k]) / F(thr[k]), a[k])
+        if d < 0:
+            continue
+        decided += 1
+        exact = S[k] * erfcx(a[k]) >= thr[k]
+        assert bool(d) == bool(exact), (S[k], a[k], thr[k])
+    assert decided > 0.45 * n
