@@ -24,24 +24,58 @@ namespace {
 
 constexpr int kOdfThreads = 256;
 
-// Bitonic network over npow2 keys.  Each step of stage (k, j) is npow2/2
-// independent compare-exchanges of the pairs (i, i + j) with bit j of i
-// clear; a thread takes pairs by pair index, so no thread idles, and writes
-// min and max back without a branch (ascending where bit k of i is clear).
+// Bitonic network over npow2 keys, up to four consecutive steps of a stage
+// per pass through memory.  Steps j = 2^h, ..., 2^l of stage k (h - l < 4)
+// only ever pair keys of a group {base + c 2^l : c < 2^(h-l+1)}, base with
+// bits l .. h clear; all keys of a group share bit k of their index, so
+// they sort in one direction (ascending where it is clear).  Each thread
+// loads whole groups into registers, runs those steps there (the same
+// compare-exchanges, in the same order, as one pass per step) and stores
+// them back: one barrier per pass instead of one per step, and a quarter of
+// the LDS traffic.
+template <int M, typename K>
+__device__ __forceinline__ void bitonic_pass(K* a, int npow2, int k, int l) {
+  constexpr int G = 1 << M;
+  const int ng = npow2 >> M;
+  const int jl = 1 << l;
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+    // g with M zero bits inserted at bit l
+    const int base = ((g >> l) << (l + M)) | (g & (jl - 1));
+    const bool up = (base & k) == 0;
+    K r[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) r[c] = a[base + c * jl];
+#pragma unroll
+    for (int t = M - 1; t >= 0; --t) {
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        if (c & (1 << t)) continue;
+        const K x = r[c], y = r[c + (1 << t)];
+        const K lo = x < y ? x : y, hi = x < y ? y : x;
+        r[c] = up ? lo : hi;
+        r[c + (1 << t)] = up ? hi : lo;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < G; ++c) a[base + c * jl] = r[c];
+  }
+}
+
 template <typename K>
 __device__ void bitonic_sort(K* a, int npow2) {
-  const int half = npow2 >> 1;
-  for (int k = 2; k <= npow2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int q = threadIdx.x; q < half; q += blockDim.x) {
-        const int i = q + (q & ~(j - 1));   // insert a zero at bit j
-        const K ai = a[i], aj = a[i + j];
-        const K lo = ai < aj ? ai : aj, hi = ai < aj ? aj : ai;
-        const bool up = (i & k) == 0;
-        a[i] = up ? lo : hi;
-        a[i + j] = up ? hi : lo;
-      }
+  int logn = 0;
+  while ((1 << logn) < npow2) ++logn;
+  for (int kl = 1; kl <= logn; ++kl) {
+    const int k = 1 << kl;
+    for (int h = kl - 1; h >= 0;) {
+      const int m = min(4, h + 1);
+      const int l = h - m + 1;
+      if (m == 4) bitonic_pass<4>(a, npow2, k, l);
+      else if (m == 3) bitonic_pass<3>(a, npow2, k, l);
+      else if (m == 2) bitonic_pass<2>(a, npow2, k, l);
+      else bitonic_pass<1>(a, npow2, k, l);
       __syncthreads();
+      h = l - 1;
     }
   }
 }
