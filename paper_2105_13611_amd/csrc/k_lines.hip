@@ -353,7 +353,7 @@ struct TFactors {
 };
 
 struct LineEval {
-  double S, a, b;
+  double S, a, b, ib;   // ib = 1 / b
   int32_t jlo, jhi;
   bool surv;
 };
@@ -412,6 +412,7 @@ __device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d
   const double thr = d.thr;
   e.S = S;
   e.b = b;
+  e.ib = ib;
   e.a = 0.0;
   e.surv = false;
   e.jlo = 0;
@@ -592,6 +593,7 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const bool valid = i < L.n;
   const int np = B.n_points;
+  const double inv_lnq = 1.0 / P.lnq;
   unsigned long long mine = 0;   // bit p: this line survives at point p
   unsigned long long wide = 0;   // bit p: ... in the wide class
   for (int p = 0; p < np; ++p) {
@@ -631,16 +633,20 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
     const int32_t J = (int32_t)Jd;
     const int64_t slot = (int64_t)p * B.rec_stride + off;
     B.win[slot] = make_int2(e.jlo, e.jhi);
-    const double c1 = P.lnq / e.b;
+    // c1 = ln q / b; the zone half-widths ceil(1.02 R / c1) + 2 as
+    // products (1 / ln q once per thread): a few ulp from the quotients,
+    // which can move a half-width only at an exact tie, where both are valid
+    const double c1 = P.lnq * e.ib;
+    const double b_lnq = e.b * inv_lnq;
     int32_t czh, z40 = -1;
     if (kRec64) {
-      czh = e.a < kFarR64 ? zone_half(kFarR64, c1) : -1;
-      z40 = e.a < kFar4R64 ? zone_half(kFar4R64, c1) : -1;
+      czh = e.a < kFarR64 ? zone_half_b(kFarR64, b_lnq) : -1;
+      z40 = e.a < kFar4R64 ? zone_half_b(kFar4R64, b_lnq) : -1;
       B.wz[slot] = make_int2(J, z40);
     } else {
       // no zone: -32768, which the Voigt kernel's row masks read as empty
-      const int32_t far = e.a < kFarR32 ? min(zone_half(kFarR32, c1), 32767) : -32768;
-      const int32_t ring = e.a < kRingR32 ? min(zone_half(kRingR32, c1), 32767) : -32768;
+      const int32_t far = e.a < kFarR32 ? min(zone_half_b(kFarR32, b_lnq), 32767) : -32768;
+      const int32_t ring = e.a < kRingR32 ? min(zone_half_b(kRingR32, b_lnq), 32767) : -32768;
       czh = (int32_t)(((uint32_t)ring << 16) | ((uint32_t)far & 0xffffu));
       B.wz[slot] = make_int2(J, czh);
     }
@@ -665,7 +671,7 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
       r.jhi = e.jhi;
       r.czh = czh;
       r.phi = (float)(d.j0s - Jd);
-      const double C1 = e.S * e.a / kSqrtPi;
+      const double C1 = e.S * e.a * (1.0 / kSqrtPi);
       if (e.a >= 1.0e4) {
         // Lorentz limit in u = x / a
         r.c1 = (float)(c1 / e.a);

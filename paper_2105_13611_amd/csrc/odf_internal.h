@@ -111,6 +111,10 @@ constexpr int kFFDist64 = 384;
 __host__ __device__ inline int32_t zone_half(double R, double c1) {
   return (int32_t)ceil(R * 1.02 / c1) + 2;
 }
+// The same from b / ln q = 1 / c1 (a product instead of a quotient).
+__host__ __device__ inline int32_t zone_half_b(double R, double b_over_lnq) {
+  return (int32_t)ceil(R * 1.02 * b_over_lnq) + 2;
+}
 
 // Quadrature constants computed on the host at plan time.
 struct QuadConsts {
