@@ -257,11 +257,16 @@ def roofline(res, flop_per_sample, precision):
     return out
 
 
+CPU_BINS = 64
+
+
 def cpu_sample(w):
-    """The CPU leg's sample: 16 stratified points of the table and three
-    bins (first, a third and two thirds along the ramp)."""
+    """The CPU leg's sample: 16 stratified points of the table and 64 bins
+    evenly spaced over the layout (the first and the last included)."""
+    import numpy as np
     nb = w.layout.n_bins
-    return stratified_points(w.points, 16), [0, nb // 3, (2 * nb) // 3]
+    k = min(CPU_BINS, nb)
+    return stratified_points(w.points, 16), [int(b) for b in np.round(np.linspace(0, nb - 1, k))]
 
 
 def cpu_baseline(w, workers):
@@ -290,7 +295,8 @@ def cpu_baseline(w, workers):
     mean_core_s = float(np.mean(core_s))
     value = workers / mean_core_s
     base = dict(value=value, unit="points/s", cores=workers, kind="oracle",
-                sample=(f"{len(idx)} stratified (T,P) points of the table x bins {bins} "
+                sample=(f"{len(idx)} stratified (T,P) points of the table x {len(bins)} bins evenly spaced "
+                        f"over the {w.layout.n_bins} "
                         f"({sum(p['samples_bins'] for p in per)} Voigt samples, wall {wall:.1f} s on "
                         f"{min(workers, len(tasks))} processes); per point the line stage is timed in "
                         f"full and the bin sums are scaled by total/sampled Voigt samples; "
@@ -351,8 +357,8 @@ def parity_block(ref, bins, legs):
     """Max relative error per ODF step and max |dlog10 kappa| of each GPU
     leg against the oracle's steps at the CPU leg's sampled pairs."""
     import numpy as np
-    out = dict(sample=f"{len(ref)} stratified (T,P) points x bins {list(bins)} of the timed table, "
-                      f"oracle steps from the CPU leg", tolerance=dict(TOL))
+    out = dict(sample=f"{len(ref)} stratified (T,P) points x {len(bins)} bins evenly spaced of the timed table "
+                      f"(first {bins[0]}, last {bins[-1]}), oracle steps from the CPU leg", tolerance=dict(TOL))
     for prec, got in legs.items():
         rel, dlog, pairs, ties, worst_tie = 0.0, 0.0, 0, 0, 0.0
         for i, r in ref.items():

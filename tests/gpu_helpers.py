@@ -50,6 +50,51 @@ def ambiguous_bins(lq, edges):
     return set(int(x) for x in b if 0 <= x < len(edges) - 1)
 
 
+class Reach:
+    """The lines whose window can reach given bins at one (T, v_turb).
+
+    A window spans at most opts.window_cap_doppler Doppler widths, and the
+    Doppler width b = sqrt(2 k T / m + v^2) / c is largest for the lightest
+    species, so at most y = cap * b_max in relative frequency on either side
+    of the centre: the window of a line at lambda_0 lies within
+    [lambda_0 / (1 + y), lambda_0 / (1 - y)].  A line can then touch a bin
+    whose points run from lambda_a to lambda_b only if
+    lambda_a (1 - y) <= lambda_0 <= lambda_b (1 + y); the bound is widened
+    by 0.1 % and a few grid steps for the window's integer rounding.  The
+    subset is a superset of the lines the oracle needs for those bins, and
+    much smaller than the whole list at cool points."""
+
+    def __init__(self, lines, species, layout, opts):
+        from oracle.constants import AMU
+        lam = np.asarray(lines.lambda_nm)
+        self.order = np.argsort(lam, kind="stable")
+        self.lam = lam[self.order]
+        self.m_min = float(np.min(species.mass_amu)) * AMU
+        self.cap = float(opts.window_cap_doppler)
+        self.layout = layout
+
+    def y(self, T, vturb_kms):
+        from oracle.constants import C_LIGHT, K_BOLTZ
+        v = vturb_kms * 1e5
+        b_max = math.sqrt(2.0 * K_BOLTZ * T / self.m_min + v * v) / C_LIGHT
+        return self.cap * b_max * 1.001 + 1e-5
+
+    def lines_for(self, bins, T, vturb_kms):
+        """Sorted indices (into the list) of the lines that can reach the bins."""
+        e = self.layout.bin_edges
+        y = self.y(T, vturb_kms)
+        parts = []
+        for b in bins:
+            l0 = float(oracle.grid_lambda_nm(self.layout, e[b]))
+            l1 = float(oracle.grid_lambda_nm(self.layout, e[b + 1] - 1))
+            i0 = np.searchsorted(self.lam, l0 * (1.0 - y), side="left")
+            i1 = np.searchsorted(self.lam, l1 * (1.0 + y), side="right")
+            parts.append(self.order[i0:i1])
+        if not parts:
+            return np.zeros(0, dtype=np.int64)
+        return np.unique(np.concatenate(parts))
+
+
 def floor_values(layout, opts, j0, j1):
     return opts.cutoff * oracle.physics.kappa_c(oracle.grid_lambda_nm(layout, np.arange(j0, j1)), opts)
 

@@ -65,12 +65,13 @@ def test_cpu_leg_keeps_the_oracle_steps():
     w = W.config(1, n_lines=300)
     base, ref, bins = bench.cpu_baseline(w, 2)
     assert base["kind"] == "oracle" and base["cores"] == 2 and base["value"] > 0
-    assert sorted(ref) == [0] and bins == [0, 6, 13]
+    # 64 evenly spaced bins, or every bin of a smaller layout (20 here)
+    assert sorted(ref) == [0] and bins == list(range(w.layout.n_bins))
     steps, _, _ = oracle.odf_point(w.lines, w.species, w.species.abundance, float(w.points.T_K[0]),
                                    float(w.points.log10_P[0]), float(w.points.vturb_kms[0]), w.layout,
                                    w.options, bins)
     np.testing.assert_array_equal(ref[0]["steps"], steps)
-    assert len(ref[0]["near_tie"]) == 3
+    assert len(ref[0]["near_tie"]) == len(bins)
 
 
 def test_traffic_summary_lookup():

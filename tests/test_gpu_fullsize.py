@@ -6,10 +6,11 @@
   the oracle checks three bins of each live.
 * The serving stream over the same list: its first four requests (own
   compositions, 762-1025 points each) submitted together to the request
-  loop, compared at 4 points x 16 bins per request with the oracle's steps
+  loop, compared at 8 points x 64 bins per request with the oracle's steps
   stored by tests/golden/make_sampled_oracle.py.
-* The 1e8-line list over 80 species x 3 stages, both precisions, at 4 points
-  x 8 bins, against the same script's stored oracle steps.
+* The 1e8-line stream over 80 species x 3 stages: its first four requests
+  (own compositions), both precisions, at 8 points x 64 bins each, against
+  the same script's stored oracle steps.
 
 A bin that holds a near-tie decision (keep test or window edge within
 rounding) is compared with the oracle recomputed with the GPU's own
@@ -25,8 +26,8 @@ import pytest
 
 import oracle
 from paper_2105_13611_amd import workload as W
-from tests.gpu_helpers import (ambiguous_bins, gpu_decisions, log10_err, oracle_bin_with_gpu_decisions,
-                               rel_err)
+from tests.gpu_helpers import (Reach, ambiguous_bins, gpu_decisions, log10_err,
+                               oracle_bin_with_gpu_decisions, rel_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +40,6 @@ POINTS = W.Points(np.array([5000.0, 2000.0, 200000.0, 20000.0, 5000.0, 20000.0])
 # bins checked per point (widths 500, 1280 and 3463 fine points)
 BINS = [0, 400, 1000]
 TOL = {"fp64": 1e-9, "mixed": 1e-3}
-REACH = 1.05   # the fixture script's pre-filter (a superset of the lines that reach a bin)
 
 
 @pytest.fixture(scope="module")
@@ -92,34 +92,34 @@ def test_full_size_sampled_parity(full, reference, prec):
     assert np.all(np.diff(got, axis=2) >= -1e-6 * np.abs(got[:, :, 1:]))
 
 
-def _reach(w, bins):
-    """The fixture script's line subset: lines within REACH of a bin."""
-    e = w.layout.bin_edges
-    lam = w.lines.lambda_nm
-    keep = np.zeros(lam.size, dtype=bool)
-    for b in bins:
-        l0 = float(oracle.grid_lambda_nm(w.layout, e[b]))
-        l1 = float(oracle.grid_lambda_nm(w.layout, e[b + 1] - 1))
-        keep |= (lam > l0 / REACH) & (lam < l1 * REACH)
-    return np.nonzero(keep)[0]
+# Recomputed references of near-tie bins, shared by the two precisions: the
+# selection (keep tests and windows) is the same kernel in both, so the GPU's
+# decisions, and the oracle's steps with them, are the same.
+_TIE_REF = {}
 
 
-def _check_pairs(w, plan, got, ref_steps, near_tie, bins, pts, abundance, tol, sub=None):
+def _check_pairs(w, plan, got, ref_steps, near_tie, bins, pts, abundance, tol, reach, key=None):
     """Max relative and log10 errors of got[k][bins] against stored oracle
-    steps; flagged bins are recomputed with the GPU's own decisions."""
+    steps; a bin flagged as holding a near-tie decision is recomputed by the
+    oracle (from the lines that can reach it) with the GPU's own decisions."""
     worst, worst_log, resolved = 0.0, 0.0, 0
     for k in range(pts.n_points):
-        lq, dec = None, None
+        dec = None
         for m, b in enumerate(bins):
             r = np.asarray(ref_steps[k][m])
             if near_tie[k][m]:
-                if lq is None:
-                    sub = _reach(w, bins) if sub is None else sub
-                    lq = oracle.line_quantities(w.lines.take(sub), w.species, abundance, float(pts.T_K[k]),
-                                                float(pts.log10_P[k]), float(pts.vturb_kms[k]), w.layout,
-                                                w.options)
-                    dec = gpu_decisions(plan, abundance, pts, k)
-                r = oracle_bin_with_gpu_decisions(lq, w.layout, w.options, b, dec, sub_to_full=sub)
+                ck = None if key is None else (key, k, b)
+                if ck in _TIE_REF:
+                    r = _TIE_REF[ck]
+                else:
+                    T, v = float(pts.T_K[k]), float(pts.vturb_kms[k])
+                    sub = reach.lines_for([b], T, v)
+                    lq = oracle.line_quantities(w.lines.take(sub), w.species, abundance, T,
+                                                float(pts.log10_P[k]), v, w.layout, w.options)
+                    dec = dec or gpu_decisions(plan, abundance, pts, k)
+                    r = oracle_bin_with_gpu_decisions(lq, w.layout, w.options, b, dec, sub_to_full=sub)
+                    if ck is not None:
+                        _TIE_REF[ck] = r
                 resolved += 1
             worst = max(worst, float(rel_err(got[k][b], r).max()))
             worst_log = max(worst_log, float(log10_err(got[k][b], r).max()))
@@ -129,7 +129,7 @@ def _check_pairs(w, plan, got, ref_steps, near_tie, bins, pts, abundance, tol, s
 
 def test_served_stream_against_oracle():
     """Four requests of the serving stream in flight together through
-    odf_submit; each result sampled at 4 points x 16 bins against the
+    odf_submit; each result sampled at 8 points x 64 bins against the
     oracle (config 4: 1e7 lines, per-request composition and points)."""
     import torch
     from paper_2105_13611_amd import odf
@@ -145,6 +145,7 @@ def test_served_stream_against_oracle():
     # a pool that holds three of these requests' footprints at once
     with odf.plan_for(w, precision="mixed", workspace_bytes=WORKSPACE) as probe:
         ws = 3 * probe.request_footprint(max(r.points.n_points for r in w.requests)) + (1 << 30)
+    reach = Reach(w.lines, w.species, w.layout, w.options)
     with odf.plan_for(w, precision="mixed", workspace_bytes=ws) as plan:
         tickets = [plan.submit(r.abundance, r.points) for r in w.requests]
         stats = [plan.wait(t, 600.0) for t, _ in tickets]
@@ -160,7 +161,7 @@ def test_served_stream_against_oracle():
             idx = np.asarray(q["point_index"])
             got = out[torch.as_tensor(idx, device=out.device)].double().cpu().numpy()
             e, el, n = _check_pairs(w, plan, got, q["steps"], q["near_tie"], bins, r.points.take(idx),
-                                    r.abundance, TOL["mixed"])
+                                    r.abundance, TOL["mixed"], reach)
             worst, worst_log, resolved = max(worst, e), max(worst_log, el), resolved + n
     lat = [s["t_done"] - s["t_submit"] for s in stats]
     print(f"served config 4: {len(stats)} requests ({sum(s['points'] for s in stats)} points), "
@@ -170,31 +171,40 @@ def test_served_stream_against_oracle():
 
 @pytest.fixture(scope="module")
 def cfg5():
-    w = W.config(5, n_requests=1)
+    fx = json.load(open(os.path.join(GOLDEN, "cfg5_sampled_oracle.json")))
+    w = W.config(5, n_requests=len(fx["requests"]))
     assert w.lines.n_lines == 100_000_000 and w.species.n_stages == 3
-    return w
+    return w, fx, Reach(w.lines, w.species, w.layout, w.options)
 
 
 @pytest.mark.slow
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_large_line_list_sampled_parity(cfg5, prec):
-    """The 1e8-line list over 80 species x 3 stages with a request's own
-    composition: 4 points of the 57 x 25 x 5 grid x 8 bins, both
-    precisions, against the stored oracle steps."""
+    """The 1e8-line stream over 80 species x 3 stages: its first four
+    requests, each with its own composition, at 8 points of the 57 x 25 x 5
+    grid x 64 bins, both precisions, against the stored oracle steps."""
     import torch
     from paper_2105_13611_amd import odf
-    fx = json.load(open(os.path.join(GOLDEN, "cfg5_sampled_oracle.json")))
-    w = cfg5
-    a = w.requests[0].abundance
-    np.testing.assert_array_equal(a, fx["abundance"])
-    pts = W.Points(np.array(fx["T_K"]), np.array(fx["log10_P"]), np.array(fx["vturb_kms"]))
+    w, fx, reach = cfg5
+    bins = fx["bins"]
+    worst, worst_log, resolved, evals = 0.0, 0.0, 0, 0
     with odf.plan_for(w, precision=prec, workspace_bytes=WORKSPACE) as plan:
-        out, st = plan.compute(a, pts)
-        got = out.double().cpu().numpy()
-        torch.cuda.synchronize()
-        worst, worst_log, resolved = _check_pairs(w, plan, got, fx["steps"], fx["near_tie"], fx["bins"], pts, a,
-                                                  TOL[prec])
-    print(f"1e8 lines {prec}: max rel err per step {worst:.3e}, max |dlog10 k| {worst_log:.3e}, "
-          f"near-tie bins {resolved}, survivors {st['survivors']}, samples {st['voigt_samples']}")
-    assert st["line_evals"] == pts.n_points * 100_000_000
-    assert np.all(np.isfinite(got)) and np.all(got > 0)
+        for q, r in zip(fx["requests"], w.requests):
+            np.testing.assert_array_equal(r.abundance, q["abundance"])
+            pts = r.points.take(np.asarray(q["point_index"]))
+            np.testing.assert_array_equal(pts.T_K, q["T_K"])
+            np.testing.assert_array_equal(pts.log10_P, q["log10_P"])
+            np.testing.assert_array_equal(pts.vturb_kms, q["vturb_kms"])
+            print(f"[1e8 lines {prec}] request {q['id']}: {pts.n_points} points", flush=True)
+            out, st = plan.compute(r.abundance, pts)
+            got = out.double().cpu().numpy()
+            torch.cuda.synchronize()
+            assert np.all(np.isfinite(got)) and np.all(got > 0)
+            e, el, n = _check_pairs(w, plan, got, q["steps"], q["near_tie"], bins, pts, r.abundance, TOL[prec],
+                                    reach, key=("cfg5", q["id"]))
+            worst, worst_log, resolved = max(worst, e), max(worst_log, el), resolved + n
+            evals += st["line_evals"]
+            assert st["line_evals"] == pts.n_points * 100_000_000
+    print(f"1e8 lines {prec}: {len(fx['requests'])} requests x {len(fx['requests'][0]['point_index'])} points x "
+          f"{len(bins)} bins, max rel err per step {worst:.3e}, max |dlog10 k| {worst_log:.3e}, "
+          f"near-tie bins {resolved}")
