@@ -17,3 +17,19 @@ def pytest_configure(config):
 def cfg1():
     from paper_2105_13611_amd import workload
     return workload.config(1)
+
+
+@pytest.fixture(scope="session")
+def progress(request):
+    """print(msg) past pytest's output capture, so that a long test reports
+    its steps while it runs (a run that stays silent for minutes cannot be
+    told from a hung one)."""
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+
+    def say(msg):
+        if capman is None:
+            print(msg, flush=True)
+            return
+        with capman.global_and_fixture_disabled():
+            print(msg, flush=True)
+    return say

@@ -98,7 +98,7 @@ def test_full_size_sampled_parity(full, reference, prec):
 _TIE_REF = {}
 
 
-def _check_pairs(w, plan, got, ref_steps, near_tie, bins, pts, abundance, tol, reach, key=None):
+def _check_pairs(w, plan, got, ref_steps, near_tie, bins, pts, abundance, tol, reach, key=None, say=None):
     """Max relative and log10 errors of got[k][bins] against stored oracle
     steps; a bin flagged as holding a near-tie decision is recomputed by the
     oracle (from the lines that can reach it) with the GPU's own decisions."""
@@ -114,6 +114,9 @@ def _check_pairs(w, plan, got, ref_steps, near_tie, bins, pts, abundance, tol, r
                 else:
                     T, v = float(pts.T_K[k]), float(pts.vturb_kms[k])
                     sub = reach.lines_for([b], T, v)
+                    if say:
+                        say(f"  near-tie bin {b} at point {k} (T={T:.0f} K): oracle with the GPU's decisions, "
+                            f"{sub.size} lines in reach")
                     lq = oracle.line_quantities(w.lines.take(sub), w.species, abundance, T,
                                                 float(pts.log10_P[k]), v, w.layout, w.options)
                     dec = dec or gpu_decisions(plan, abundance, pts, k)
@@ -127,7 +130,7 @@ def _check_pairs(w, plan, got, ref_steps, near_tie, bins, pts, abundance, tol, r
     return worst, worst_log, resolved
 
 
-def test_served_stream_against_oracle():
+def test_served_stream_against_oracle(progress):
     """Four requests of the serving stream in flight together through
     odf_submit; each result sampled at 8 points x 64 bins against the
     oracle (config 4: 1e7 lines, per-request composition and points)."""
@@ -160,8 +163,9 @@ def test_served_stream_against_oracle():
         for q, r, (t, out) in zip(fx["requests"], w.requests, tickets):
             idx = np.asarray(q["point_index"])
             got = out[torch.as_tensor(idx, device=out.device)].double().cpu().numpy()
+            progress(f"[served config 4] request {q['id']}: {len(idx)} points x {len(bins)} bins")
             e, el, n = _check_pairs(w, plan, got, q["steps"], q["near_tie"], bins, r.points.take(idx),
-                                    r.abundance, TOL["mixed"], reach)
+                                    r.abundance, TOL["mixed"], reach, say=progress)
             worst, worst_log, resolved = max(worst, e), max(worst_log, el), resolved + n
     lat = [s["t_done"] - s["t_submit"] for s in stats]
     print(f"served config 4: {len(stats)} requests ({sum(s['points'] for s in stats)} points), "
@@ -170,16 +174,19 @@ def test_served_stream_against_oracle():
 
 
 @pytest.fixture(scope="module")
-def cfg5():
+def cfg5(progress):
     fx = json.load(open(os.path.join(GOLDEN, "cfg5_sampled_oracle.json")))
+    progress("[1e8 lines] generating the seeded 1e8-line workload")
     w = W.config(5, n_requests=len(fx["requests"]))
     assert w.lines.n_lines == 100_000_000 and w.species.n_stages == 3
-    return w, fx, Reach(w.lines, w.species, w.layout, w.options)
+    progress("[1e8 lines] sorting the line list for the per-bin reach")
+    reach = Reach(w.lines, w.species, w.layout, w.options)
+    return w, fx, reach
 
 
 @pytest.mark.slow
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_large_line_list_sampled_parity(cfg5, prec):
+def test_large_line_list_sampled_parity(cfg5, prec, progress):
     """The 1e8-line stream over 80 species x 3 stages: its first four
     requests, each with its own composition, at 8 points of the 57 x 25 x 5
     grid x 64 bins, both precisions, against the stored oracle steps."""
@@ -188,6 +195,7 @@ def test_large_line_list_sampled_parity(cfg5, prec):
     w, fx, reach = cfg5
     bins = fx["bins"]
     worst, worst_log, resolved, evals = 0.0, 0.0, 0, 0
+    progress(f"[1e8 lines {prec}] plan")
     with odf.plan_for(w, precision=prec, workspace_bytes=WORKSPACE) as plan:
         for q, r in zip(fx["requests"], w.requests):
             np.testing.assert_array_equal(r.abundance, q["abundance"])
@@ -195,13 +203,13 @@ def test_large_line_list_sampled_parity(cfg5, prec):
             np.testing.assert_array_equal(pts.T_K, q["T_K"])
             np.testing.assert_array_equal(pts.log10_P, q["log10_P"])
             np.testing.assert_array_equal(pts.vturb_kms, q["vturb_kms"])
-            print(f"[1e8 lines {prec}] request {q['id']}: {pts.n_points} points", flush=True)
+            progress(f"[1e8 lines {prec}] request {q['id']}: {pts.n_points} points")
             out, st = plan.compute(r.abundance, pts)
             got = out.double().cpu().numpy()
             torch.cuda.synchronize()
             assert np.all(np.isfinite(got)) and np.all(got > 0)
             e, el, n = _check_pairs(w, plan, got, q["steps"], q["near_tie"], bins, pts, r.abundance, TOL[prec],
-                                    reach, key=("cfg5", q["id"]))
+                                    reach, key=("cfg5", q["id"]), say=progress)
             worst, worst_log, resolved = max(worst, e), max(worst_log, el), resolved + n
             evals += st["line_evals"]
             assert st["line_evals"] == pts.n_points * 100_000_000
