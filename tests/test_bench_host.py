@@ -65,8 +65,8 @@ def test_cpu_leg_keeps_the_oracle_steps():
     w = W.config(1, n_lines=300)
     base, ref, bins = bench.cpu_baseline(w, 2)
     assert base["kind"] == "oracle" and base["cores"] == 2 and base["value"] > 0
-    # 64 evenly spaced bins, or every bin of a smaller layout (20 here)
-    assert sorted(ref) == [0] and bins == list(range(w.layout.n_bins))
+    # CPU_BINS evenly spaced bins, or every bin of a smaller layout (20 here)
+    assert sorted(ref) == [0] and bins == list(range(min(bench.CPU_BINS, w.layout.n_bins)))
     steps, _, _ = oracle.odf_point(w.lines, w.species, w.species.abundance, float(w.points.T_K[0]),
                                    float(w.points.log10_P[0]), float(w.points.vturb_kms[0]), w.layout,
                                    w.options, bins)
