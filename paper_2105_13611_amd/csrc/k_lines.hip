@@ -382,7 +382,7 @@ __device__ __forceinline__ bool keep_line(double S, double a, double thr) {
 // take the FP64 test.
 __device__ __forceinline__ int keep_line32(float rf, float af) {
   constexpr float kSqrtPiF = 1.77245385f;
-  if (!(rf < 1e30f)) return -1;
+  if (!(rf < 1e30f) || !(af < 1e15f)) return -1;   // outside the FP32 ranges assumed below
   const float lo = 2.0f / (kSqrtPiF * (af + sqrtf(fmaf(af, af, 2.0f))));
   if (rf * lo >= 1.0f + 1e-5f) return 1;
   const float hi = 2.0f / (kSqrtPiF * (af + sqrtf(fmaf(af, af, (float)(4.0 / kPi)))));

@@ -24,7 +24,7 @@ def fmaf(a, b, c):
 def keep32(rf, af):
     """keep_line32: 1 keep, 0 drop, -1 undecided."""
     rf, af = F(rf), F(af)
-    if not rf < F(1e30):
+    if not (rf < F(1e30) and af < F(1e15)):
         return -1
     sp = F(1.77245385)
     lo = F(2.0) / (sp * (af + np.sqrt(fmaf(af, af, 2.0))))
@@ -53,3 +53,10 @@ def test_keep_decisions_equal_fp64():
         exact = S[k] * erfcx(a[k]) >= thr[k]
         assert bool(d) == bool(exact), (S[k], a[k], thr[k])
     assert decided > 0.45 * n
+
+
+def test_keep_leaves_out_of_range_inputs_to_fp64():
+    """Damping or strength ratios beyond the FP32 ranges the bounds assume
+    (a^2 would overflow) are left to the FP64 test, never decided here."""
+    for rf, af in ((1e25, 1e19), (1e31, 1.0), (np.inf, 1.0), (2.0, 3e38)):
+        assert keep32(F(rf), af) == -1
