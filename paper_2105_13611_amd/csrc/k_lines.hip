@@ -322,6 +322,7 @@ hipError_t launch_point_state(hipStream_t st, const Params& P, const Batch& B) {
 // Per-line constants, loaded once and reused for every point of a batch.
 struct LineData {
   double j0s, amp, e_k, hc_k, g_rad, g_stark, g_vdw, thr;
+  double ithr, inv_lnq;   // 1/thr and 1/ln q, set by the selection for its window
   int32_t sp, ss;
 };
 
@@ -429,11 +430,15 @@ __device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d
     const int k32 = keep_line32((float)S / (float)thr, (float)a);
     if (k32 == 0 || (k32 < 0 && !keep_line64(S, a, thr))) return e;
   }
-  const double xg = sqrt(fmax(0.0, log(2.0 * S / thr)));
-  const double xl = sqrt(2.0 * S * a / (kSqrtPi * thr));
+  // the window's quotients as products (1/thr once per line and batch, 1/ln q
+  // once per thread): a few ulp from the quotients, which can move an edge
+  // only where its real value sits on an integer, where either is valid
+  const double r = S * d.ithr;
+  const double xg = sqrt(fmax(0.0, log(2.0 * r)));
+  const double xl = sqrt((2.0 / kSqrtPi) * r * a);
   const double xw = fmin(P.cap, fmax(xg, xl));
-  const double lo = ceil(d.j0s - log1p(xw * b) / P.lnq);
-  const double hi = floor(d.j0s - log1p(-xw * b) / P.lnq);
+  const double lo = ceil(d.j0s - log1p(xw * b) * d.inv_lnq);
+  const double hi = floor(d.j0s - log1p(-xw * b) * d.inv_lnq);
   const double jl = fmax(lo, 0.0);
   const double jh = fmin(hi, (double)(P.N - 1));
   if (jl > jh) return e;
@@ -459,7 +464,11 @@ __global__ __launch_bounds__(kLineBlock) void k_select(Params P, DevLines L, Bat
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const bool valid = i < L.n;
   LineData d{};
-  if (valid) d = load_line(L, i);
+  if (valid) {
+    d = load_line(L, i);
+    d.ithr = 1.0 / d.thr;
+    d.inv_lnq = 1.0 / P.lnq;
+  }
   const int32_t J = (int32_t)rint(d.j0s);
   TFactors tf;
   const int np = B.n_points;
