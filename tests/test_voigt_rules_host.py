@@ -11,7 +11,7 @@ the rule.  The bounds are the ones the kernels' designs rest on:
   FP32  two-node pair fraction      |z| >= 15                5e-5
         the same, Lorentz limit     a >= 1e4                 1/(2 a^2)
         four-node pair sum          |z| >= 6                 2e-5
-        pole-corrected trapezoid    a in [0.4, 15), |x| <= 30   5e-6
+        pole-corrected trapezoid    a in [0.4, 15), |x| <= 70   5e-6
         (h = 0.75, 13 nodes, |t| <= 4.2)
         small-damping series        a < 0.4, any x           1e-5
   FP64  four-node pair sum          |z| >= 40                3e-12
@@ -126,7 +126,8 @@ def test_fp32_four_node_pair_sum():
 
 @pytest.mark.parametrize("a", [0.4, 0.6, 1.0, 2.0, 3.5, 4.18, 4.2, 6.0, 10.0, 14.9])
 def test_fp32_trapezoid(a):
-    x = np.concatenate([np.linspace(0.0, 30.0, 3001), np.linspace(0.0, 3.0, 401) + 1e-3])
+    # core rows reach |x| = 6 + 64 points, up to about 70 Doppler widths at one point per width
+    x = np.concatenate([np.linspace(0.0, 70.0, 7001), np.linspace(0.0, 3.0, 401) + 1e-3])
     got = trapezoid(x, np.full_like(x, a), 0.75, 6, 4.2)
     assert rel(got, H(x, np.full_like(x, a))) <= 5e-6
 
