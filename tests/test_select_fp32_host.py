@@ -60,3 +60,31 @@ def test_keep_leaves_out_of_range_inputs_to_fp64():
     (a^2 would overflow) are left to the FP64 test, never decided here."""
     for rf, af in ((1e25, 1e19), (1e31, 1.0), (np.inf, 1.0), (2.0, 3e38)):
         assert keep32(F(rf), af) == -1
+
+
+def log1p_pm(v):
+    """ln(1 + v) and ln(1 - v) from the odd and even parts of the series of
+    ln(1 + v), as the selection evaluates them for |v| <= 1/16 (odd part to
+    v^13, even part to v^12, Horner in v^2)."""
+    w = v * v
+    o = 1.0 / 13
+    for c in (11, 9, 7, 5, 3, 1):
+        o = o * w + 1.0 / c
+    o = o * v
+    e = 1.0 / 12
+    for c in (10, 8, 6, 4, 2):
+        e = e * w + 1.0 / c
+    e = -e * w
+    return e + o, e - o
+
+
+def test_log1p_pair_series():
+    """Within 4 ulp of the library log1p over |v| <= 1/16 (edges of the
+    window move by at most that times their distance from the centre, far
+    below the 1e-7 points where a window edge counts as a tie)."""
+    v = np.concatenate([np.linspace(-1.0 / 16, 1.0 / 16, 200001), np.geomspace(1e-12, 1.0 / 16, 2001)])
+    v = v[v != 0.0]
+    lp, lm = log1p_pm(v)
+    assert np.max(np.abs(lp / np.log1p(v) - 1.0)) <= 4 * 2.0 ** -52
+    assert np.max(np.abs(lm / np.log1p(-v) - 1.0)) <= 4 * 2.0 ** -52
+    assert log1p_pm(0.0) == (0.0, 0.0)
