@@ -376,19 +376,28 @@ __device__ __forceinline__ bool keep_line(double S, double a, double thr) {
   return S * erfcx(a) >= thr;
 }
 
-// The keep test in FP32 first: r = S / thr and a rounded to FP32 (within
-// 3 and 1 ulp), and the erfcx bounds above evaluated in FP32 (within about
-// 8 ulp, 5e-7), decide every line whose r erfcx(a) is more than 1e-5 away
-// from 1 the same way as the FP64 test.  1: keep, 0: drop, -1: too close,
-// take the FP64 test.
+// The keep test in FP32 first: r = S / thr and a rounded to FP32 (within 1
+// ulp each), and the erfcx bounds above compared in FP32 as products,
+// 2 r >= (1 + 1e-5) sqrt(pi) (a + sqrt(a^2 + 2)) to keep and
+// 2 r < (1 - 1e-5) sqrt(pi) (a + sqrt(a^2 + 4/pi)) to drop (within about
+// 6 ulp, 4e-7, with the hardware square root's 1 ulp): they decide every
+// line whose r erfcx(a) is more than 1e-5 away from 1 the same way as the
+// FP64 test.  1: keep, 0: drop, -1: too close, take the FP64 test.
 __device__ __forceinline__ int keep_line32(float rf, float af) {
   constexpr float kSqrtPiF = 1.77245385f;
   if (!(rf < 1e30f) || !(af < 1e15f)) return -1;   // outside the FP32 ranges assumed below
-  const float lo = 2.0f / (kSqrtPiF * (af + sqrtf(fmaf(af, af, 2.0f))));
-  if (rf * lo >= 1.0f + 1e-5f) return 1;
-  const float hi = 2.0f / (kSqrtPiF * (af + sqrtf(fmaf(af, af, (float)(4.0 / kPi)))));
-  if (rf * hi < 1.0f - 1e-5f) return 0;
+  const float r2 = 2.0f * rf;
+  if (r2 >= ((1.0f + 1e-5f) * kSqrtPiF) * (af + __builtin_amdgcn_sqrtf(fmaf(af, af, 2.0f)))) return 1;
+  if (r2 < ((1.0f - 1e-5f) * kSqrtPiF) * (af + __builtin_amdgcn_sqrtf(fmaf(af, af, (float)(4.0 / kPi)))))
+    return 0;
   return -1;
+}
+
+// The library's ln(1 + v) and ln(1 - v), out of line: the window below
+// needs them only for |v| > 1/16, which no line of a stellar list reaches,
+// and inlined they would hold registers that the common path needs.
+__device__ __attribute__((noinline)) double2 log1p_pair_lib(double v) {
+  return make_double2(log1p(v), log1p(-v));
 }
 
 // ln(1 + v) and ln(1 - v) for the window's v = x_w b (500 Doppler widths
@@ -417,8 +426,9 @@ __device__ __forceinline__ void log1p_pm(double v, double& lp, double& lm) {
     lp = e + o;
     lm = e - o;
   } else {
-    lp = log1p(v);
-    lm = log1p(-v);
+    const double2 l = log1p_pair_lib(v);
+    lp = l.x;
+    lm = l.y;
   }
 }
 
@@ -458,16 +468,18 @@ __device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d
     return e;
   }
   if (!kKept) {
-    const int k32 = keep_line32((float)S / (float)thr, (float)a);
+    const int k32 = keep_line32((float)(S * d.ithr), (float)a);
     if (k32 == 0 || (k32 < 0 && !keep_line64(S, a, thr))) return e;
   }
   // the window's quotients as products (1/thr once per line and batch, 1/ln q
   // once per thread): a few ulp from the quotients, which can move an edge
   // only where its real value sits on an integer, where either is valid
+  // x_w = min(cap, max(x_G, x_L)) with x_G = sqrt(max(0, ln 2r)) and
+  // x_L = sqrt(2 r a / sqrt(pi)): one square root of the larger radicand
+  // (sqrt is correctly rounded, so monotone, and gives the same value; the
+  // Lorentz radicand is never negative, so it also stands for the 0)
   const double r = S * d.ithr;
-  const double xg = sqrt(fmax(0.0, log(2.0 * r)));
-  const double xl = sqrt((2.0 / kSqrtPi) * r * a);
-  const double xw = fmin(P.cap, fmax(xg, xl));
+  const double xw = fmin(P.cap, sqrt(fmax(log(2.0 * r), (2.0 / kSqrtPi) * r * a)));
   double lp, lm;
   log1p_pm(xw * b, lp, lm);
   const double lo = ceil(d.j0s - lp * d.inv_lnq);
@@ -484,8 +496,9 @@ __device__ __forceinline__ LineEval eval_line(const Params& P, const LineData& d
 constexpr int kWavesK1 = kLineBlock / 64;
 
 // Selection: one thread per line, looping over the batch's points so the
-// line's constants are read once per batch.  Writes the keep flags (1: a
-// narrow survivor, half-window at most kNarrowHalf; 2: a wide one), the
+// line's constants are read once per batch.  Writes each line's keep masks
+// over the batch's points (kept; kept in the wide class, half-window above
+// kNarrowHalf) with one store per line, the
 // per-(point, class, block) survivor counts, and per point each class's
 // largest half-window and the number of Voigt samples.
 __global__ __launch_bounds__(kLineBlock) void k_select(Params P, DevLines L, Batch B) {
@@ -505,8 +518,16 @@ __global__ __launch_bounds__(kLineBlock) void k_select(Params P, DevLines L, Bat
   const int32_t J = (int32_t)rint(d.j0s);
   TFactors tf;
   const int np = B.n_points;
+  unsigned long long kept = 0, kwide = 0;
+  // the point state through the constant address space (scalar loads; the
+  // kernel does not write it)
+  typedef const __attribute__((address_space(4))) PointState cps;
+  const cps* state = (const cps*)B.state;
   for (int p = 0; p < np; ++p) {
-    const PointState ps = B.state[p];
+    PointState ps{};   // the fields the line's strength and damping use
+    ps.T = state[p].T;
+    ps.cS = state[p].cS;
+    ps.cW = state[p].cW;
     bool s = false, nar = false;
     int32_t half = 0;
     unsigned long long ns = 0;
@@ -520,8 +541,9 @@ __global__ __launch_bounds__(kLineBlock) void k_select(Params P, DevLines L, Bat
         ns = (unsigned long long)(e.jhi - e.jlo + 1);
         nar = half <= kNarrowHalf;
         B.wline[(int64_t)p * B.rec_stride + i] = make_int2(e.jlo, e.jhi);
+        kept |= 1ull << p;
+        if (!nar) kwide |= 1ull << p;
       }
-      B.flags[(int64_t)p * B.rec_stride + i] = s ? (nar ? 1 : 2) : 0;
     }
     const unsigned long long mn = __ballot(s && nar), mw = __ballot(s && !nar);
     int32_t hn = nar ? half : 0, hw = (s && !nar) ? half : 0;
@@ -540,6 +562,7 @@ __global__ __launch_bounds__(kLineBlock) void k_select(Params P, DevLines L, Bat
       wn[p][wid] = ns;
     }
   }
+  if (valid) B.keep[i] = make_ulonglong2(kept, kwide);
   __syncthreads();
   for (int p = threadIdx.x; p < np; p += blockDim.x) {
     int32_t cn = 0, cw = 0, hn = 0, hw = 0;
@@ -623,10 +646,15 @@ hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const
   return hipGetLastError();
 }
 
-// Survivor emission: the intra-block prefix of the flags gives each kept
-// line its slot after the block's offset, so the survivor list keeps the
-// wavelength order (stable compaction, no atomics on positions).  One thread
-// per line, looping over the batch's points.
+// Survivor emission: the intra-block prefix of the keep masks gives each
+// kept line its slot after the block's offset, so the survivor list keeps
+// the wavelength order (stable compaction, no atomics on positions).  One
+// thread per line, looping over the batch's points.  The per-point values
+// every lane shares (the block's offsets, the narrow count, the point state)
+// are read through the constant address space: nothing in this kernel writes
+// them, and uniform constant loads are scalar loads, issued together with
+// one wait (through a generic pointer the record stores make the compiler
+// use a vector load and a wait for each).
 template <bool kRec64>
 __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch B) {
   __shared__ int32_t wc[2][kMaxBatch][kWavesK1];
@@ -636,13 +664,12 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
   const bool valid = i < L.n;
   const int np = B.n_points;
   const double inv_lnq = 1.0 / P.lnq;
-  unsigned long long mine = 0;   // bit p: this line survives at point p
-  unsigned long long wide = 0;   // bit p: ... in the wide class
+  const ulonglong2 km = valid ? B.keep[i] : make_ulonglong2(0ull, 0ull);
+  const unsigned long long mine = km.x;   // bit p: this line survives at point p
+  const unsigned long long wide = km.y;   // bit p: ... in the wide class
   for (int p = 0; p < np; ++p) {
-    const uint8_t f = valid ? B.flags[(int64_t)p * B.rec_stride + i] : (uint8_t)0;
-    if (f) mine |= 1ull << p;
-    if (f == 2) wide |= 1ull << p;
-    const unsigned long long mn = __ballot(f == 1), mw = __ballot(f == 2);
+    const bool f = (mine >> p) & 1ull, w = (wide >> p) & 1ull;
+    const unsigned long long mn = __ballot(f && !w), mw = __ballot(w);
     if (lane == 0) {
       wc[0][p][wid] = __popcll(mn);
       wc[1][p][wid] = __popcll(mw);
@@ -650,6 +677,11 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
   }
   __syncthreads();
   if (!__ballot(mine != 0ull)) return;
+  typedef const __attribute__((address_space(4))) int32_t ci32;
+  typedef const __attribute__((address_space(4))) PointState cps;
+  const ci32* blk = (const ci32*)B.blk;
+  const ci32* nsn = (const ci32*)B.nsurv_n;
+  const cps* state = (const cps*)B.state;
   LineData d{};
   if (valid) d = load_line(L, i);
   TFactors tf;
@@ -659,12 +691,16 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
     const int cls = (int)((wide >> p) & 1ull);
     const unsigned long long mn = __ballot(f && cls == 0), mw = __ballot(f && cls == 1);
     if (!(mn | mw)) continue;
+    const int32_t off_n = blk[((int64_t)p * 2 + 0) * nblk + blockIdx.x];
+    const int32_t off_w = blk[((int64_t)p * 2 + 1) * nblk + blockIdx.x] + nsn[p];
+    PointState ps{};   // the fields the line's strength and damping use
+    ps.T = state[p].T;
+    ps.cS = state[p].cS;
+    ps.cW = state[p].cW;
     if (!f) continue;
-    int32_t off = B.blk[((int64_t)p * 2 + cls) * nblk + blockIdx.x];
+    int32_t off = cls ? off_w : off_n;
     for (int w = 0; w < wid; ++w) off += wc[cls][p][w];
     off += __popcll((cls ? mw : mn) & below);
-    if (cls) off += B.nsurv_n[p];
-    const PointState ps = B.state[p];
     tf.update(d, ps.T);
     LineEval e = eval_line<true, false>(P, d, ps, tf, B.pop + (int64_t)p * P.n_species * P.n_stages,
                                         B.bT + (int64_t)p * 2 * P.n_species);

@@ -222,7 +222,7 @@ struct Batch {
   PointState* state;    // [B]
   double* pop;          // [B][S*K]
   double* bT;           // [B][S][2]: b and 1/b
-  uint8_t* flags;       // [B][L]       0: dropped, 1: narrow survivor, 2: wide survivor
+  ulonglong2* keep;     // [L]          per line, bit p of x: kept at point p; of y: kept in the wide class
   int2* wline;          // [B][L]       survivors' windows (j_lo, j_hi) by line, from the selection
   int32_t* blk;         // [B][2][nblk] counts per class, then offsets within the class
   int32_t* nsurv;       // [B]         survivors (both classes)

@@ -215,7 +215,7 @@ SlotLayout make_slot(const odf_plan_s* p, int32_t pts) {
   s.off_state = take((int64_t)sizeof(PointState) * pts);
   s.off_pop = take(8 * S * K * pts);
   s.off_bT = take(16 * S * pts);   // (b, 1/b) per species
-  s.off_flags = take(std::max<int64_t>(L, 1) * pts);
+  s.off_keep = take(16 * std::max<int64_t>(L, 1));
   s.off_wline = take((int64_t)sizeof(int2) * std::max<int64_t>(L, 1) * pts);
   s.off_blk = take(4 * 2 * std::max<int64_t>(nblk, 1) * pts);
   s.off_nsurv = take(4 * pts);
@@ -244,7 +244,7 @@ Batch make_batch(const odf_plan_s* p, const SlotLayout& s, char* base, int32_t n
   B.state = reinterpret_cast<PointState*>(base + s.off_state);
   B.pop = reinterpret_cast<double*>(base + s.off_pop);
   B.bT = reinterpret_cast<double*>(base + s.off_bT);
-  B.flags = reinterpret_cast<uint8_t*>(base + s.off_flags);
+  B.keep = reinterpret_cast<ulonglong2*>(base + s.off_keep);
   B.wline = reinterpret_cast<int2*>(base + s.off_wline);
   B.blk = reinterpret_cast<int32_t*>(base + s.off_blk);
   B.nsurv = reinterpret_cast<int32_t*>(base + s.off_nsurv);

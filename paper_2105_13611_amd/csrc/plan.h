@@ -24,7 +24,7 @@ void g_last_error_clear();
 
 // Layout of one batch slot inside the workspace.
 struct SlotLayout {
-  int64_t off_T, off_logP, off_vt, off_abund, off_state, off_pop, off_bT, off_flags, off_wline, off_blk,
+  int64_t off_T, off_logP, off_vt, off_abund, off_state, off_pop, off_bT, off_keep, off_wline, off_blk,
       off_nsurv, off_nsurv_n, off_hmax, off_hmax_w, off_nsamp, off_nit, off_rec, off_win, off_wz,
       off_kappa, off_gscr;
   int64_t bytes;      // total bytes of the slot

@@ -4,8 +4,10 @@ The selection kernel decides the keep test S erfcx(a) >= thr in FP32 first:
 the classical erfcx bounds evaluated in FP32 settle every line whose
 S erfcx(a) / thr is more than 1e-5 away from 1, and the FP64 test takes the
 rest.  This test runs the same FP32 operations in numpy float32 (one
-rounding per operation) on lines spread around the keep boundary (damping
-1e-5 to 1e5, half of them within 1e-3 of it): wherever the FP32 test
+rounding per operation; the square roots, which the kernel takes from the
+hardware within 1 ulp, moved by a random ulp) on lines spread around the
+keep boundary (damping 1e-5 to 1e5, half of them within 1e-3 of it):
+wherever the FP32 test
 decides, its decision must equal the exact one (scipy's erfcx, Sec. 2.1 and
 App. E); and it must decide for most lines, or it would not pay.
 """
@@ -21,17 +23,23 @@ def fmaf(a, b, c):
     return F(np.float64(a) * np.float64(b) + np.float64(c))
 
 
+def sqrt1ulp(x, rng=np.random.default_rng(7)):
+    """FP32 square root within 1 ulp (the hardware's v_sqrt_f32): the
+    correctly rounded root moved by a random -1, 0 or +1 ulp."""
+    s = np.sqrt(F(x))
+    return np.nextafter(s, F(np.inf) if rng.random() < 0.5 else F(0)) if rng.random() < 2 / 3 else s
+
+
 def keep32(rf, af):
     """keep_line32: 1 keep, 0 drop, -1 undecided."""
     rf, af = F(rf), F(af)
     if not (rf < F(1e30) and af < F(1e15)):
         return -1
     sp = F(1.77245385)
-    lo = F(2.0) / (sp * (af + np.sqrt(fmaf(af, af, 2.0))))
-    if rf * lo >= F(1.0) + F(1e-5):
+    r2 = F(2.0) * rf
+    if r2 >= (F(1.0) + F(1e-5)) * sp * (af + sqrt1ulp(fmaf(af, af, 2.0))):
         return 1
-    hi = F(2.0) / (sp * (af + np.sqrt(fmaf(af, af, F(4.0 / math.pi)))))
-    if rf * hi < F(1.0) - F(1e-5):
+    if r2 < (F(1.0) - F(1e-5)) * sp * (af + sqrt1ulp(fmaf(af, af, F(4.0 / math.pi)))):
         return 0
     return -1
 
@@ -46,7 +54,7 @@ def test_keep_decisions_equal_fp64():
     S = q / erfcx(a) * thr
     decided = 0
     for k in range(n):
-        d = keep32(F(S[k]) / F(thr[k]), a[k])
+        d = keep32(F(S[k] * (1.0 / thr[k])), a[k])
         if d < 0:
             continue
         decided += 1
