@@ -649,24 +649,32 @@ hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const
 // Survivor emission: the intra-block prefix of the keep masks gives each
 // kept line its slot after the block's offset, so the survivor list keeps
 // the wavelength order (stable compaction, no atomics on positions).  One
-// thread per line, looping over the batch's points.  The per-point values
+// thread per line and chunk of kEmitChunk points (the grid's y), looping over
+// the chunk's points: the offsets are per point and block of lines, so the
+// chunks are independent, and short loops keep more loads in flight than one
+// loop over the batch (each point waits for its loads).  The per-point values
 // every lane shares (the block's offsets, the narrow count, the point state)
 // are read through the constant address space: nothing in this kernel writes
 // them, and uniform constant loads are scalar loads, issued together with
 // one wait (through a generic pointer the record stores make the compiler
 // use a vector load and a wait for each).
+constexpr int kEmitChunk = 8;
+
 template <bool kRec64>
 __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch B) {
-  __shared__ int32_t wc[2][kMaxBatch][kWavesK1];
+  __shared__ int32_t wc[2][kEmitChunk][kWavesK1];
   const int64_t i = (int64_t)blockIdx.x * kLineBlock + threadIdx.x;
   const int64_t nblk = gridDim.x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const bool valid = i < L.n;
-  const int np = B.n_points;
+  const int p0 = (int)blockIdx.y * kEmitChunk;
+  const int np = min(B.n_points - p0, kEmitChunk);
   const double inv_lnq = 1.0 / P.lnq;
   const ulonglong2 km = valid ? B.keep[i] : make_ulonglong2(0ull, 0ull);
-  const unsigned long long mine = km.x;   // bit p: this line survives at point p
-  const unsigned long long wide = km.y;   // bit p: ... in the wide class
+  // bit p: this line survives at point p0 + p of the batch; wide: ... in the wide class
+  const unsigned long long cm = (1ull << np) - 1ull;
+  const unsigned long long mine = (km.x >> p0) & cm;
+  const unsigned long long wide = (km.y >> p0) & cm;
   for (int p = 0; p < np; ++p) {
     const bool f = (mine >> p) & 1ull, w = (wide >> p) & 1ull;
     const unsigned long long mn = __ballot(f && !w), mw = __ballot(w);
@@ -686,11 +694,12 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
   if (valid) d = load_line(L, i);
   TFactors tf;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int p = 0; p < np; ++p) {
-    const bool f = (mine >> p) & 1ull;
-    const int cls = (int)((wide >> p) & 1ull);
+  for (int pc = 0; pc < np; ++pc) {
+    const bool f = (mine >> pc) & 1ull;
+    const int cls = (int)((wide >> pc) & 1ull);
     const unsigned long long mn = __ballot(f && cls == 0), mw = __ballot(f && cls == 1);
     if (!(mn | mw)) continue;
+    const int p = p0 + pc;   // the point in the batch
     const int32_t off_n = blk[((int64_t)p * 2 + 0) * nblk + blockIdx.x];
     const int32_t off_w = blk[((int64_t)p * 2 + 1) * nblk + blockIdx.x] + nsn[p];
     PointState ps{};   // the fields the line's strength and damping use
@@ -699,7 +708,7 @@ __global__ __launch_bounds__(kLineBlock) void k_emit(Params P, DevLines L, Batch
     ps.cW = state[p].cW;
     if (!f) continue;
     int32_t off = cls ? off_w : off_n;
-    for (int w = 0; w < wid; ++w) off += wc[cls][p][w];
+    for (int w = 0; w < wid; ++w) off += wc[cls][pc][w];
     off += __popcll((cls ? mw : mn) & below);
     tf.update(d, ps.T);
     LineEval e = eval_line<true, false>(P, d, ps, tf, B.pop + (int64_t)p * P.n_species * P.n_stages,
@@ -776,10 +785,11 @@ hipError_t launch_emit(hipStream_t st, const Params& P, const DevLines& L, const
   if (B.n_points == 0 || L.n == 0) return hipSuccess;
   if (B.n_points > kMaxBatch) return hipErrorInvalidValue;
   const int64_t nblk = n_line_blocks(L.n);
+  const dim3 grid((unsigned)nblk, (unsigned)((B.n_points + kEmitChunk - 1) / kEmitChunk));
   if (rec64)
-    hipLaunchKernelGGL(k_emit<true>, dim3((unsigned)nblk), dim3(kLineBlock), 0, st, P, L, B);
+    hipLaunchKernelGGL(k_emit<true>, grid, dim3(kLineBlock), 0, st, P, L, B);
   else
-    hipLaunchKernelGGL(k_emit<false>, dim3((unsigned)nblk), dim3(kLineBlock), 0, st, P, L, B);
+    hipLaunchKernelGGL(k_emit<false>, grid, dim3(kLineBlock), 0, st, P, L, B);
   return hipGetLastError();
 }
 
