@@ -14,6 +14,12 @@
 // they are bitonic-sorted in LDS, padded with all-ones keys to a power of
 // two.  Bins too large for LDS sort in a global scratch slab with the same
 // network.  Step sums are FP64 in a fixed reduction order.
+//
+// In LDS, key i sits at i + i / (128 B / key size): one unused key after
+// every 128 bytes.  The passes that load 16 consecutive keys per thread
+// (the last pass of every stage) would otherwise put the lanes of a
+// half-wave on 2 of the 32 banks (u32 keys; 1 of 16 bank pairs for u64);
+// with the gap they fall on distinct banks.
 #include <algorithm>
 
 #include "odf_internal.h"
@@ -33,7 +39,18 @@ constexpr int kOdfThreads = 256;
 // compare-exchanges, in the same order, as one pass per step) and stores
 // them back: one barrier per pass instead of one per step, and a quarter of
 // the LDS traffic.
-template <int M, typename K>
+template <bool kPad, typename K>
+__device__ __forceinline__ int kidx(int i) {
+  return kPad ? i + (i >> (sizeof(K) == 4 ? 5 : 4)) : i;
+}
+
+// keys in LDS for a bin of npow2 keys (with the gaps)
+template <typename K>
+__host__ __device__ inline int lds_keys(int npow2) {
+  return npow2 + (npow2 >> (sizeof(K) == 4 ? 5 : 4));
+}
+
+template <int M, bool kPad, typename K>
 __device__ __forceinline__ void bitonic_pass(K* a, int npow2, int k, int l) {
   constexpr int G = 1 << M;
   const int ng = npow2 >> M;
@@ -44,7 +61,7 @@ __device__ __forceinline__ void bitonic_pass(K* a, int npow2, int k, int l) {
     const bool up = (base & k) == 0;
     K r[G];
 #pragma unroll
-    for (int c = 0; c < G; ++c) r[c] = a[base + c * jl];
+    for (int c = 0; c < G; ++c) r[c] = a[kidx<kPad, K>(base + c * jl)];
 #pragma unroll
     for (int t = M - 1; t >= 0; --t) {
 #pragma unroll
@@ -57,11 +74,11 @@ __device__ __forceinline__ void bitonic_pass(K* a, int npow2, int k, int l) {
       }
     }
 #pragma unroll
-    for (int c = 0; c < G; ++c) a[base + c * jl] = r[c];
+    for (int c = 0; c < G; ++c) a[kidx<kPad, K>(base + c * jl)] = r[c];
   }
 }
 
-template <typename K>
+template <bool kPad, typename K>
 __device__ void bitonic_sort(K* a, int npow2) {
   int logn = 0;
   while ((1 << logn) < npow2) ++logn;
@@ -70,10 +87,10 @@ __device__ void bitonic_sort(K* a, int npow2) {
     for (int h = kl - 1; h >= 0;) {
       const int m = min(4, h + 1);
       const int l = h - m + 1;
-      if (m == 4) bitonic_pass<4>(a, npow2, k, l);
-      else if (m == 3) bitonic_pass<3>(a, npow2, k, l);
-      else if (m == 2) bitonic_pass<2>(a, npow2, k, l);
-      else bitonic_pass<1>(a, npow2, k, l);
+      if (m == 4) bitonic_pass<4, kPad>(a, npow2, k, l);
+      else if (m == 3) bitonic_pass<3, kPad>(a, npow2, k, l);
+      else if (m == 2) bitonic_pass<2, kPad>(a, npow2, k, l);
+      else bitonic_pass<1, kPad>(a, npow2, k, l);
       __syncthreads();
       h = l - 1;
     }
@@ -101,6 +118,48 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return t;
 }
 
+// Floor, sort and sub-bin means of bin b at point p, its keys in a (LDS with
+// gaps where kPad, else a global slab).
+template <bool kPad, typename T, typename K>
+__device__ __forceinline__ void odf_bin(const Params& P, const T* __restrict__ kp, T* __restrict__ out,
+                                        int b, int p, int64_t e0, int n, int npow2, K* a,
+                                        double* red) {
+  for (int i = threadIdx.x; i < npow2; i += blockDim.x) {
+    K key = ~(K)0;
+    if (i < n) {
+      const int64_t j = e0 + i;
+      const double lam = P.lambda_first_nm * exp((double)j * P.lnq);
+      const double fl = P.cutoff * (P.kc_ref * pow(lam / P.kc_lref, P.kc_power));
+      const T v = kp[j];
+      const T f = (T)fl;
+      key = value_key(v > f ? v : f);
+    }
+    a[kidx<kPad, K>(i)] = key;
+  }
+  __syncthreads();
+  bitonic_sort<kPad>(a, npow2);
+  const int S = P.n_steps;
+  const double dn = (double)n;
+  for (int s = 0; s < S; ++s) {
+    const double lo = P.Fcum[s] * dn, hi = P.Fcum[s + 1] * dn;
+    const int i0 = (int)floor(lo);
+    const int i1 = min(n, (int)ceil(hi));
+    double acc = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      const double w = fmin((double)(i + 1), hi) - fmax((double)i, lo);
+      if (w > 0.0) {
+        const double v = key_value(a[kidx<kPad, K>(i)]);
+        acc += w * (P.mean == 0 ? log(v) : v);
+      }
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+      const double m = tot / (hi - lo);
+      out[((int64_t)p * P.n_bins + b) * S + s] = (T)(P.mean == 0 ? exp(m) : m);
+    }
+  }
+}
+
 template <typename T, typename K>
 __global__ __launch_bounds__(kOdfThreads) void k_odf(Params P, const T* __restrict__ kappa,
                                                      int64_t kappa_stride, T* __restrict__ out,
@@ -115,48 +174,12 @@ __global__ __launch_bounds__(kOdfThreads) void k_odf(Params P, const T* __restri
   const int n = (int)(e1 - e0);
   int npow2 = 1;
   while (npow2 < n) npow2 <<= 1;
-  K* a;
-  if (npow2 <= lds_cap) {
-    a = reinterpret_cast<K*>(smem);
-  } else {
-    // bins too large for LDS: a private slab of the global scratch
-    a = gscratch + (int64_t)p * gscratch_stride + goff[b];
-  }
   const T* kp = kappa + (int64_t)p * kappa_stride;
-  for (int i = threadIdx.x; i < npow2; i += blockDim.x) {
-    K key = ~(K)0;
-    if (i < n) {
-      const int64_t j = e0 + i;
-      const double lam = P.lambda_first_nm * exp((double)j * P.lnq);
-      const double fl = P.cutoff * (P.kc_ref * pow(lam / P.kc_lref, P.kc_power));
-      const T v = kp[j];
-      const T f = (T)fl;
-      key = value_key(v > f ? v : f);
-    }
-    a[i] = key;
-  }
-  __syncthreads();
-  bitonic_sort(a, npow2);
-  const int S = P.n_steps;
-  const double dn = (double)n;
-  for (int s = 0; s < S; ++s) {
-    const double lo = P.Fcum[s] * dn, hi = P.Fcum[s + 1] * dn;
-    const int i0 = (int)floor(lo);
-    const int i1 = min(n, (int)ceil(hi));
-    double acc = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-      const double w = fmin((double)(i + 1), hi) - fmax((double)i, lo);
-      if (w > 0.0) {
-        const double v = key_value(a[i]);
-        acc += w * (P.mean == 0 ? log(v) : v);
-      }
-    }
-    const double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) {
-      const double m = tot / (hi - lo);
-      out[((int64_t)p * P.n_bins + b) * S + s] = (T)(P.mean == 0 ? exp(m) : m);
-    }
-  }
+  if (npow2 <= lds_cap)
+    odf_bin<true>(P, kp, out, b, p, e0, n, npow2, reinterpret_cast<K*>(smem), red);
+  else   // bins too large for LDS: a private slab of the global scratch
+    odf_bin<false>(P, kp, out, b, p, e0, n, npow2,
+                   gscratch + (int64_t)p * gscratch_stride + goff[b], red);
 }
 
 // Pre-tabulated high-resolution opacity (Sec. 4.1): every fine point is a
@@ -207,20 +230,24 @@ hipError_t launch_odf(hipStream_t st, const Params& P, const void* kappa, int64_
     const int cnt = C.count[c];
     if (cnt == 0) continue;
     const int npow2 = C.npow2[c];
-    const size_t shmem = npow2 <= lds_cap ? (size_t)npow2 * key_bytes : 0;
+    const size_t shmem =
+        npow2 <= lds_cap ? (size_t)(P.precision == 1 ? lds_keys<uint32_t>(npow2) : lds_keys<uint64_t>(npow2)) * key_bytes
+                         : 0;
+    const int max_shmem =
+        (P.precision == 1 ? lds_keys<uint32_t>(lds_cap) : lds_keys<uint64_t>(lds_cap)) * key_bytes;
     dim3 grid(cnt, n_points);
     const int32_t* bins = C.bins + C.offset[c];
     if (P.precision == 1) {
       auto k = k_odf<float, uint32_t>;
       hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)(lds_cap * key_bytes));
+                                         max_shmem);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k, grid, dim3(kOdfThreads), shmem, st, P, (const float*)kappa, kappa_stride,
                          (float*)out, bins, lds_cap, (uint32_t*)gscratch, goff, gscratch_stride);
     } else {
       auto k = k_odf<double, uint64_t>;
       hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)(lds_cap * key_bytes));
+                                         max_shmem);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k, grid, dim3(kOdfThreads), shmem, st, P, (const double*)kappa,
                          kappa_stride, (double*)out, bins, lds_cap, (uint64_t*)gscratch, goff,
