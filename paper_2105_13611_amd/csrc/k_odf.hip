@@ -7,7 +7,9 @@
 // contributes to sub-bin s with the length of its overlap with
 // [F_{s-1} n, F_s n), so fractional sub-bin borders are exact.  Values are
 // floored at cutoff * kappa_c(lambda_j) first: below it the line opacity is
-// not resolved by the pre-selection (Sec. 4.3).
+// not resolved by the pre-selection (Sec. 4.3); the plan tabulates that
+// floor once per fine point (k_floor), in the path's type, and both the ODF
+// and the pre-tabulated output read it.
 //
 // One workgroup per (bin, point).  Keys are the raw bits of the positive
 // floored values (FP32 as u32, FP64 as u64), which order like the values;
@@ -124,14 +126,13 @@ template <bool kPad, typename T, typename K>
 __device__ __forceinline__ void odf_bin(const Params& P, const T* __restrict__ kp, T* __restrict__ out,
                                         int b, int p, int64_t e0, int n, int npow2, K* a,
                                         double* red) {
+  const T* __restrict__ fl = static_cast<const T*>(P.floor);
   for (int i = threadIdx.x; i < npow2; i += blockDim.x) {
     K key = ~(K)0;
     if (i < n) {
       const int64_t j = e0 + i;
-      const double lam = P.lambda_first_nm * exp((double)j * P.lnq);
-      const double fl = P.cutoff * (P.kc_ref * pow(lam / P.kc_lref, P.kc_power));
       const T v = kp[j];
-      const T f = (T)fl;
+      const T f = fl[j];
       key = value_key(v > f ? v : f);
     }
     a[kidx<kPad, K>(i)] = key;
@@ -182,10 +183,21 @@ __global__ __launch_bounds__(kOdfThreads) void k_odf(Params P, const T* __restri
                    gscratch + (int64_t)p * gscratch_stride + goff[b], red);
 }
 
+// The floor cutoff * kappa_c(lambda_j), kappa_c = kc_ref (lambda / kc_lref)^kc_power
+// at lambda_j = lambda_1 q^j, rounded once to the path's type.
+template <typename T>
+__global__ __launch_bounds__(256) void k_floor(Params P, T* __restrict__ out) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < P.N;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const double lam = P.lambda_first_nm * exp((double)j * P.lnq);
+    out[j] = (T)(P.cutoff * (P.kc_ref * pow(lam / P.kc_lref, P.kc_power)));
+  }
+}
+
 // Pre-tabulated high-resolution opacity (Sec. 4.1): every fine point is a
 // bin of its own with one sub-bin, whose mean is the floored value itself.
-// The floor is taken exactly as in k_odf, so the result equals, bit for bit,
-// the arithmetic-mean ODF of one-point bins.  Memory-bound: one read and one
+// The floor is the table k_odf reads, so the result equals, bit for bit, the
+// arithmetic-mean ODF of one-point bins.  Memory-bound: two reads and one
 // write per fine point, coalesced, one point of the batch per grid row.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fine(Params P, const T* __restrict__ kappa,
@@ -193,17 +205,26 @@ __global__ __launch_bounds__(256) void k_fine(Params P, const T* __restrict__ ka
   const int p = blockIdx.y;
   const T* kp = kappa + (int64_t)p * kappa_stride;
   T* op = out + (int64_t)p * P.N;
+  const T* __restrict__ fl = static_cast<const T*>(P.floor);
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < P.N;
        j += (int64_t)gridDim.x * blockDim.x) {
-    const double lam = P.lambda_first_nm * exp((double)j * P.lnq);
-    const double fl = P.cutoff * (P.kc_ref * pow(lam / P.kc_lref, P.kc_power));
     const T v = kp[j];
-    const T f = (T)fl;
+    const T f = fl[j];
     op[j] = v > f ? v : f;
   }
 }
 
 }  // namespace
+
+hipError_t launch_floor(hipStream_t st, const Params& P, void* floor) {
+  if (P.N == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((P.N + 255) / 256, 4096);
+  if (P.precision == 1)
+    hipLaunchKernelGGL(k_floor<float>, dim3((unsigned)blocks), dim3(256), 0, st, P, (float*)floor);
+  else
+    hipLaunchKernelGGL(k_floor<double>, dim3((unsigned)blocks), dim3(256), 0, st, P, (double*)floor);
+  return hipGetLastError();
+}
 
 hipError_t launch_fine(hipStream_t st, const Params& P, const void* kappa, int64_t kappa_stride,
                        int32_t n_points, void* out) {

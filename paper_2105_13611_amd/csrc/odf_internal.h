@@ -254,6 +254,7 @@ struct Params {
   int32_t n_bins, n_steps;
   const int64_t* edges;    // device [n_bins+1]
   const double* Fcum;      // device [n_steps+1] cumulative fractions, F[0]=0, F[n]=1
+  const void* floor;       // device [N], float (mixed) or double: cutoff * kappa_c(lambda_j)
   int32_t mean;            // 0 geometric, 1 arithmetic
   int32_t precision;       // 0 fp64, 1 mixed
   int32_t output;          // 0 ODF table, 1 fine-grid opacity
@@ -274,6 +275,9 @@ hipError_t launch_select(hipStream_t st, const Params& P, const DevLines& L, con
 hipError_t launch_scan(hipStream_t st, const Params& P, const DevLines& L, const Batch& B);
 hipError_t launch_emit(hipStream_t st, const Params& P, const DevLines& L, const Batch& B, int rec64);
 hipError_t launch_voigt(hipStream_t st, const Params& P, const Batch& B, const QuadConsts* Q);
+// The opacity floor cutoff * kappa_c(lambda_j) at every fine point, in the
+// path's type, into P.floor (once per plan).
+hipError_t launch_floor(hipStream_t st, const Params& P, void* floor);
 // Floored fine-grid opacity of n_points grids (kappa rows kappa_stride apart)
 // into out [n_points][N].
 hipError_t launch_fine(hipStream_t st, const Params& P, const void* kappa, int64_t kappa_stride,

@@ -597,6 +597,24 @@ odf_status odf_plan(const odf_lines* lines, const odf_species* species, const od
     P.output = p->opts.output == ODF_OUT_FINE ? 1 : 0;
     P.electrons = p->opts.electrons == ODF_NE_EQUILIBRIUM ? 1 : 0;
     P.ne_max_iter = kNeMaxSteps;
+    // the opacity floor per fine point, tabulated once
+    void* fl = nullptr;
+    if (P.precision == 1) {
+      float* f = nullptr;
+      st = dev_alloc(pp, &f, std::max<int64_t>(p->N, 1));
+      fl = f;
+    } else {
+      double* f = nullptr;
+      st = dev_alloc(pp, &f, std::max<int64_t>(p->N, 1));
+      fl = f;
+    }
+    if (st != ODF_OK) { free_owned(pp); return st; }
+    P.floor = fl;
+    if ((e = launch_floor(s0, P, fl)) != hipSuccess || (e = hipStreamSynchronize(s0)) != hipSuccess) {
+      set_error("opacity floor tabulation failed: %s", hipGetErrorString(e));
+      free_owned(pp);
+      return ODF_E_DEVICE;
+    }
   }
   p->quad = make_quad_consts();
   {
