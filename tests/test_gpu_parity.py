@@ -195,6 +195,28 @@ def test_batching_and_pipeline_slots_do_not_change_results(odf, multi, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_full_batch_and_point_chunks(odf, multi, prec):
+    """Selection keeps one 64-bit mask per line over a batch's points and
+    emission takes the points in chunks of 8 (the grid's second dimension):
+    64 points in one batch (every mask bit, eight full chunks), in batches of
+    19 (chunks of 8, 8 and a ragged 3) and one at a time must give the same
+    bits."""
+    rng = np.random.default_rng(64)
+    n = 64
+    pts = W.Points(10.0 ** rng.uniform(np.log10(2500.0), np.log10(100000.0), n),
+                   rng.uniform(-2.0, 7.0, n), rng.uniform(0.0, 8.0, n))
+    w = replace(multi, points=pts)
+    outs = []
+    for mb in (64, 19, 1):
+        with odf.plan_for(w, precision=prec, workspace_bytes=2 << 30, max_batch_points=mb) as plan:
+            out, st = plan.compute(w.species.abundance, w.points)
+            outs.append(out.clone())
+            assert st["points"] == n
+    assert bool((outs[1] == outs[0]).all())
+    assert bool((outs[2] == outs[0]).all())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_deterministic(plans1, cfg1, prec):
     w = cfg1
     a, _ = plans1[prec].compute(w.species.abundance, w.points)
