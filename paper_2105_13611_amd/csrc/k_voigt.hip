@@ -95,7 +95,10 @@ __device__ __forceinline__ float ring32(float x, float y, const QuadConsts* __re
 
 // Pole-corrected trapezoidal rule, nodes t_k = (k + delta) h, for y < 6 and
 // |x| up to about 30 (the running product is renormalised once so that it
-// stays inside the FP32 range).
+// stays inside the FP32 range).  The node k = kTrap32Half lies beyond the
+// rule's |t| <= kTrap32Tmax in both grids (weight zero), so the loop stops
+// before it.
+static_assert((float)kTrap32Half * kTrap32H > kTrap32Tmax, "last FP32 trapezoid node has weight zero");
 __device__ __forceinline__ float core32(float x, float y, const QuadConsts* __restrict__ Q) {
   constexpr float h = kTrap32H;
   constexpr float invh = 1.0f / kTrap32H;
@@ -103,12 +106,11 @@ __device__ __forceinline__ float core32(float x, float y, const QuadConsts* __re
   const float hx = x * invh;
   const float fr = hx - rintf(hx);
   const bool sh = fabsf(fr) < 0.25f;
-  const float delta = sh ? 0.5f : 0.0f;
+  const float xs = sh ? x - 0.5f * h : x;   // x - delta h: node k then sits at k h
   float num = 0.0f, den = 1.0f;
 #pragma unroll
-  for (int k = -kTrap32Half; k <= kTrap32Half; ++k) {
-    const float t = ((float)k + delta) * h;
-    const float dd = x - t;
+  for (int k = -kTrap32Half; k < kTrap32Half; ++k) {
+    const float dd = xs - (float)k * h;
     const float D = fmaf(dd, dd, y2);
     const float ck = sh ? Q->tr32_ch[k + kTrap32Half] : Q->tr32_ci[k + kTrap32Half];
     num = fmaf(num, D, ck * den);
@@ -744,7 +746,9 @@ __device__ __forceinline__ double gh4_value(double X, const Gh4Frac& f) {
 }
 
 // Pole-corrected trapezoidal rule (FP64), any x reached by a core row; ep is
-// the line's e^{-2 pi a / h}.
+// the line's e^{-2 pi a / h}.  As in FP32, the node k = kTrap64Half has
+// weight zero in both grids and is left out.
+static_assert(kTrap64Half * kTrap64H > kTrap64Tmax, "last FP64 trapezoid node has weight zero");
 __device__ __forceinline__ double core64(double x, double y, double ep, const QuadConsts* __restrict__ Q) {
   constexpr double h = kTrap64H;
   constexpr double invh = 1.0 / kTrap64H;
@@ -755,7 +759,7 @@ __device__ __forceinline__ double core64(double x, double y, double ep, const Qu
   const double xs = sh ? x - 0.5 * h : x;   // x - delta h: node k then sits at k h
   double num = 0.0, den = 1.0;
 #pragma unroll
-  for (int k = -kTrap64Half; k <= kTrap64Half; ++k) {
+  for (int k = -kTrap64Half; k < kTrap64Half; ++k) {
     const double dd = xs - (double)k * h;
     const double D = fma(dd, dd, y2);
     const double ck = sh ? Q->tr64_ch[k + kTrap64Half] : Q->tr64_ci[k + kTrap64Half];
