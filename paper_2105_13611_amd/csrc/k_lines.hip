@@ -394,14 +394,16 @@ __device__ __forceinline__ int keep_line32(float rf, float af) {
 }
 
 // The library's ln(1 + v) and ln(1 - v), out of line: the window below
-// needs them only for |v| > 1/16, which no line of a stellar list reaches,
-// and inlined they would hold registers that the common path needs.
+// needs them only for |v| > 1/16, which only the strongest hydrogen lines
+// reach, above about 100 000 K, and inlined they would hold registers that
+// the common path needs.
 __device__ __attribute__((noinline)) double2 log1p_pair_lib(double v) {
   return make_double2(log1p(v), log1p(-v));
 }
 
-// ln(1 + v) and ln(1 - v) for the window's v = x_w b (500 Doppler widths
-// of b <= 1e-4 give |v| <= 0.05): from the odd and even parts of the series
+// ln(1 + v) and ln(1 - v) for the window's v = x_w b (x_w <= 500 Doppler
+// widths; b is below 1e-4 for every species up to 50 000 K and reaches about
+// 1.9e-4 for hydrogen at 200 000 K): from the odd and even parts of the series
 // of ln(1 + v), truncated after v^13 and v^12 (the next terms are below
 // 1e-18 of the sum for |v| <= 1/16), within 2 ulp of log1p; the library
 // log1p beyond.
