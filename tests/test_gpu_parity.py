@@ -81,6 +81,34 @@ def test_k1_line_strengths(plans1, cfg1, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_k1_windows_beyond_the_series_range(odf, cfg1, prec):
+    """The selection takes ln(1 +- x_w b) from a series for |x_w b| <= 1/16
+    and from the library log1p beyond.  Strong microturbulence (60 and 80
+    km/s: b about 2e-4 and 2.7e-4 for every species) with the 500-Doppler
+    width cap puts hundreds of survivors beyond, beside thousands below:
+    survivors and both window edges must match the oracle's, near-ties
+    excused as in the stage test above."""
+    w = replace(cfg1, options=replace(cfg1.options, window_cap_doppler=500.0),
+                points=W.small_points([6000.0, 20000.0], [4.0, 2.0], [60.0, 80.0]))
+    with odf.plan_for(w, precision=prec, workspace_bytes=256 << 20) as plan:
+        for i in range(w.points.n_points):
+            res = plan.stage_lines(w.species.abundance, w.points, i)
+            lq = _lq(w, i)
+            v = lq["xw"] * lq["b"]
+            assert (lq["surv"] & (v > 1.0 / 16)).sum() >= 100 and (lq["surv"] & (v <= 1.0 / 16)).sum() >= 1000
+            keep_tie, lo_tie, hi_tie = ambiguous_lines(lq)
+            so = set(np.nonzero(lq["surv"])[0].tolist())
+            sg = set(res["orig"].tolist())
+            for k in so ^ sg:
+                assert keep_tie[k] or lo_tie[k] or hi_tie[k], f"line {k} kept differently without a near-tie"
+            idx = res["orig"]
+            m = np.array([k in so for k in idx])
+            o = idx[m]
+            assert ((res["jlo"][m] == lq["jlo"][o]) | lo_tie[o]).all()
+            assert ((res["jhi"][m] == lq["jhi"][o]) | hi_tie[o]).all()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_k3_fine_grid(plans1, cfg1, prec):
     w = cfg1
     lq = _lq(w)
